@@ -1,0 +1,181 @@
+/*
+ * sht.h -- C ABI of the MI355X (gfx950) inverse spherical harmonic transform.
+ *
+ * The transform synthesises real maps on iso-latitude rings from harmonic
+ * coefficients (Hupca, Falcou, Grigori, Stompor, "Spherical harmonic
+ * transform with GPUs", INRIA RR-7409):
+ *
+ *   s(theta, phi) = sum_{l=0}^{lmax} sum_{m=-l}^{l} a_lm Y_lm(theta, phi)     Eq. (alm2mapDef)
+ *
+ * computed in two stages: the Legendre stage
+ *
+ *   Delta_m(theta_r) = sum_{l=m}^{lmax} a_lm P_lm(cos theta_r)                Eq. (DeltaDef)
+ *
+ * (the two-point recurrence of Eq. (assLegRec) run on the fly with
+ * real-time rescaling, Sec. 2.2.2, Algorithm 2) and, per ring, the Fourier
+ * sum s(theta_r, phi) = sum_m e^{i m phi} Delta_m(theta_r) (Eq. Delta2map)
+ * with modes wrapped modulo the ring's pixel count (Sec. 2.2.2).
+ *
+ * Conventions
+ *  - Orthonormal P_lm without Condon-Shortley phase (mu_m > 0, Eq. pmm).
+ *  - Only m >= 0 is stored; a_{l,-m} = (-1)^m conj(a_lm) (Sec. 2.1).  The
+ *    imaginary part of a_l0 is ignored on input and written as 0 on output.
+ *  - Coefficients: complex128 interleaved (re, im), m-major packed: for the
+ *    i-th m of the m-set, l = m..lmax are contiguous, starting at
+ *    off_i = sum_{j<i} (lmax - m_j + 1).  nalm = off_nm.
+ *  - Maps: float64, RING order; pixel j of ring r sits at ringstart[r] + j and
+ *    at azimuth phi0[r] + 2 pi j / nphi[r].
+ *  - Batches: nmaps maps share one geometry; map b's coefficients start at
+ *    alm + 2 * b * nalm (doubles), its pixels at map + b * npix.
+ *
+ * Ownership and streams
+ *  - The plan owns only its own device tables, allocated on the device that
+ *    is current when sht_plan is called.  Every device pointer passed to the
+ *    other calls (coefficients, maps, workspace) is owned by the caller and
+ *    must be on that device, 16-byte aligned.
+ *  - sht_alm2map* and sht_alm2map_adjoint* only enqueue kernels on `stream`
+ *    (a hipStream_t; NULL is the null stream).  They never allocate memory
+ *    and never synchronise, so they can be captured into a HIP graph.
+ *  - A plan is immutable after creation.  Calls on different streams are
+ *    safe if they use distinct workspaces.
+ *
+ * Errors: every call returns an sht_status; nothing throws across the ABI.
+ * Argument errors are detected on the host before anything is enqueued.
+ * A device-side failure shows up as SHT_ERR_HIP on the call that observes it.
+ */
+#ifndef SHT_H
+#define SHT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sht_plan_s *sht_plan_t;
+
+typedef enum {
+    SHT_OK = 0,
+    SHT_ERR_INVALID_ARG = -1, /* a descriptor field or pointer is invalid       */
+    SHT_ERR_OOM = -2,         /* host or device allocation failed (plan only)   */
+    SHT_ERR_HIP = -3,         /* a HIP runtime call failed                      */
+    SHT_ERR_UNSUPPORTED = -4, /* valid request this build does not implement    */
+    SHT_ERR_BAD_HANDLE = -5,  /* NULL, destroyed or foreign plan handle         */
+    SHT_ERR_WORKSPACE = -6    /* workspace NULL or smaller than required        */
+} sht_status;
+
+typedef enum {
+    SHT_FP64 = 0 /* FP64 recurrence and FP64 accumulation */
+} sht_precision;
+
+#define SHT_MAX_LMAX 16383
+/* largest ring the per-ring Fourier kernels hold in LDS:
+ * even nphi: nphi/2 <= 8192 if nphi/2 factors into 2,3,5,7, else nphi/2 <= 4096;
+ * odd nphi: nphi <= 8192 if it factors into 3,5,7, else nphi <= 4096. */
+#define SHT_MAX_NPHI 16384
+
+/* Geometry and problem description for sht_plan.  All pointers are host
+ * pointers; sht_plan copies what it needs, so they may be freed afterwards. */
+typedef struct {
+    int32_t lmax;             /* band limit, 0 <= lmax <= SHT_MAX_LMAX               */
+    int32_t nm;               /* number of m in the m-set, 1 <= nm <= lmax + 1      */
+    const int32_t *mval;      /* [nm] strictly increasing, 0 <= m <= lmax;
+                                 NULL means m = 0, 1, ..., nm - 1                   */
+    int32_t nrings;           /* >= 1                                               */
+    const double *cth;        /* [nrings] cos(theta_r), in [-1, 1]                  */
+    const double *sth;        /* [nrings] sin(theta_r) >= 0, cth^2 + sth^2 = 1 (1e-12) */
+    const double *phi0;       /* [nrings] azimuth of the first pixel of ring r      */
+    const int64_t *nphi;      /* [nrings] pixels in ring r, 1..SHT_MAX_NPHI          */
+    const int64_t *ringstart; /* [nrings] first pixel of ring r; NULL = packed in
+                                 ring order.  Rings may not overlap.                */
+    int32_t nmaps;            /* maps per call, >= 1                                */
+    int32_t precision;        /* sht_precision                                      */
+    uint32_t flags;           /* SHT_FLAG_*                                         */
+} sht_geometry_desc;
+
+/* Treat every ring on its own even when its mirror ring (cth negated
+ * bitwise, sth equal) is present.  Results are the same up to rounding. */
+#define SHT_FLAG_NO_PAIRING 1u
+
+typedef struct {
+    int64_t nalm;             /* complex coefficients per map                       */
+    int64_t npix;             /* pixels per map (max of ringstart + nphi)           */
+    int32_t nrings;
+    int32_t npairs;           /* recurrence units: mirror pairs + unpaired rings    */
+    int32_t nm;
+    int32_t lmax;
+    int32_t mmax;
+    int32_t nmaps;
+    size_t workspace_bytes;   /* for sht_alm2map / sht_alm2map_adjoint              */
+    size_t delta_bytes;       /* nmaps * nrings * nm * 16                          */
+    size_t table_bytes;       /* device memory held by the plan                     */
+} sht_plan_info;
+
+/* Build a plan: validate the descriptor, pair mirror rings, precompute the
+ * recurrence tables (mu_m of Eq. pmm, beta_lm of Eq. betaDef folded into the
+ * normalised form described in the library source) and the per-ring Fourier
+ * tables, and upload them to the current device.
+ * Returns SHT_ERR_INVALID_ARG for a bad descriptor, SHT_ERR_UNSUPPORTED for a
+ * ring longer than the kernels support, SHT_ERR_OOM / SHT_ERR_HIP on
+ * allocation failure.  *out is NULL on failure. */
+sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *desc);
+
+/* Release the plan's device tables.  The handle is invalid afterwards;
+ * passing it again returns SHT_ERR_BAD_HANDLE (best effort).  Work still
+ * queued that uses the plan must have completed. */
+sht_status sht_plan_destroy(sht_plan_t plan);
+
+sht_status sht_plan_get_info(sht_plan_t plan, sht_plan_info *info);
+
+/* Bytes of device workspace sht_alm2map and sht_alm2map_adjoint need. */
+sht_status sht_plan_workspace_size(sht_plan_t plan, size_t *bytes);
+
+/* alm2map (Eq. alm2mapDef): alm device complex128 [nmaps][nalm] (read),
+ * map device float64 [nmaps][npix] (written at every ring pixel; pixels not
+ * covered by any ring are left untouched), ws device scratch of at least
+ * sht_plan_workspace_size bytes (contents on entry ignored). */
+sht_status sht_alm2map(sht_plan_t plan, const double *alm, double *map,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* sht_alm2map that also records caller-created HIP events (hipEvent_t) on
+ * `stream` at its stage boundaries, for stage timing:
+ * events[0] before the coefficient prescale, events[1] before the Legendre
+ * kernel, events[2] before the ring synthesis, events[3] after it.
+ * events must hold 4 valid events; otherwise as sht_alm2map. */
+sht_status sht_alm2map_events(sht_plan_t plan, const double *alm, double *map,
+                              void *ws, size_t ws_bytes, void *stream,
+                              void *const *events);
+
+/* Adjoint of sht_alm2map with respect to the real inner products
+ * <map, map'> = sum_p map_p map'_p and <a, a'> = sum Re(conj(a) a') over the
+ * stored coefficients: alm_lm = c_m sum_p map_p P_lm(cos theta_p) e^{-i m phi_p},
+ * c_0 = 1, c_{m>0} = 2 -- the gradient of a real loss of the map with respect
+ * to (Re a_lm, Im a_lm), packed as complex.  map device float64 [nmaps][npix]
+ * (read), alm device complex128 [nmaps][nalm] (written; Im of m = 0 is 0). */
+sht_status sht_alm2map_adjoint(sht_plan_t plan, const double *map, double *alm,
+                               void *ws, size_t ws_bytes, void *stream);
+
+/* The two stages on their own (same kernels as sht_alm2map).
+ * delta: device complex128 [nmaps][nrings][nm], Delta_m(theta_r) of
+ * Eq. (DeltaDef) for the i-th m of the set at [b][r][i]. */
+sht_status sht_alm2delta(sht_plan_t plan, const double *alm, double *delta,
+                         void *ws, size_t ws_bytes, void *stream);
+sht_status sht_delta2map(sht_plan_t plan, const double *delta, double *map, void *stream);
+
+/* Adjoint stages: map -> Delta~ (ring analysis) and Delta~ -> alm. */
+sht_status sht_map2delta_adjoint(sht_plan_t plan, const double *map, double *delta,
+                                 void *stream);
+sht_status sht_delta2alm_adjoint(sht_plan_t plan, const double *delta, double *alm,
+                                 void *ws, size_t ws_bytes, void *stream);
+
+/* Static description of a status code. */
+const char *sht_status_string(sht_status status);
+
+/* Library version, "major.minor.patch". */
+const char *sht_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHT_H */

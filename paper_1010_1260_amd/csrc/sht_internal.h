@@ -1,0 +1,90 @@
+// Internal declarations shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "sht.h"
+
+namespace sht {
+
+constexpr uint64_t kPlanMagic = 0x53485450'4c414e31ull;  // "SHTPLAN1"
+constexpr uint64_t kDeadMagic = 0xdeadbeefdeadbeefull;
+
+// Values of the Legendre recurrence are carried as v * 2^(kScaleStep * k),
+// k <= 0 (Sec. 2.2.2: real-time rescaling).  A value is rescaled when its
+// magnitude exceeds 2^kScaleStep; checks happen every 8 steps, over which
+// the normalised recurrence grows by less than 2^140 for l <= 16383, so
+// |v| < 2^652 always.  Terms with k <= -2 are below 2^-372 and dropped.
+constexpr int kScaleStep = 512;
+
+// Per-ring description for the Fourier kernels (device side).
+struct RingDesc {
+    long long start;  // first pixel of the ring in the map
+    long long tw;     // offset (double2) of e^{+2 pi i k / n}, k < n
+    long long tch;    // offset of e^{+2 pi i q / (2 clen)}, q < 2 clen (Bluestein chirp)
+    long long twb;    // offset of e^{+2 pi i k / nb}, k < nb (Bluestein FFT)
+    long long bq;     // offset of the Bluestein kernel spectrum (nb entries)
+    double phi0;
+    int n;            // pixels in the ring
+    int clen;         // complex FFT length: n / 2 (n even) or n (n odd)
+    int nb;           // Bluestein convolution length (power of two), 0 if clen is 7-smooth
+    int pad;
+};
+
+// One recurrence unit: a ring, or a ring and its mirror (cos negated,
+// same sin), processed together through the parity P_lm(-x) = (-1)^(l+m) P_lm(x).
+struct PairDesc {
+    double x;     // cos(theta) of the northern member
+    double s;     // sin(theta)
+    int rn;       // ring index of the northern member
+    int rs;       // ring index of the southern member, -1 if unpaired
+};
+
+}  // namespace sht
+
+struct sht_plan_s {
+    uint64_t magic;
+    int device;
+    int lmax, mmax, nm, nrings, nmaps, npairs, precision;
+    uint32_t flags;
+    long long nalm, npix;
+    std::vector<int32_t> mval;
+    std::vector<long long> moff;
+    // device tables (owned by the plan)
+    sht::PairDesc *d_pairs;
+    int32_t *d_mval;
+    long long *d_moff;
+    double *d_mu;        // mu_m for each m of the set (Eq. pmm)
+    double *d_A;         // [nalm] normalised recurrence coefficient, see legendre.hip
+    double *d_cn;        // [nalm] normalisation c_lm folded into the coefficients
+    int32_t *d_minv;     // [mmax + 1] index of m in the set, -1 if absent
+    sht::RingDesc *d_rings;
+    double2 *d_pool;     // twiddle and Bluestein tables
+    size_t table_bytes;
+    size_t pool_entries;
+    int lds_complex;     // LDS double2 entries the Fourier kernels need
+    int ring_block;      // threads per workgroup of the Fourier kernels
+    size_t ws_ap_bytes;  // workspace: prescaled coefficients
+    size_t ws_delta_bytes;
+};
+
+namespace sht {
+
+// Launchers (legendre.hip / ringfft.hip).  All enqueue on `st` only.
+hipError_t launch_prescale(const sht_plan_s *p, const double *alm, double2 *ap, hipStream_t st);
+hipError_t launch_legendre_fwd(const sht_plan_s *p, const double2 *ap, double2 *delta,
+                               hipStream_t st);
+hipError_t launch_legendre_adj_ws(const sht_plan_s *p, const double2 *dt, double2 *part,
+                                  double *alm, hipStream_t st);
+size_t adj_part_bytes(const sht_plan_s *p);
+hipError_t launch_ring_synth(const sht_plan_s *p, const double2 *delta, double *map,
+                             hipStream_t st);
+hipError_t launch_ring_anal(const sht_plan_s *p, const double *map, double2 *dt, hipStream_t st);
+// Plan time: spectra of the Bluestein chirp kernels.
+hipError_t launch_bluestein_prep(const sht_plan_s *p, const int *ring_ids, int nids,
+                                 hipStream_t st);
+
+}  // namespace sht

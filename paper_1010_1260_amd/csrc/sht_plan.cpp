@@ -1,0 +1,499 @@
+// Host runtime of the C ABI declared in sht.h: descriptor validation, ring
+// pairing, recurrence and Fourier tables, workspace layout and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+#include "sht_internal.h"
+
+using sht::PairDesc;
+using sht::RingDesc;
+
+namespace {
+
+constexpr int kMaxLds = 8193;  // double2 entries of LDS a Fourier workgroup may use
+
+bool smooth7(long long n)
+{
+    if (n < 1) return false;
+    for (int p : {2, 3, 5, 7})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+int next_pow2(long long n)
+{
+    int v = 1;
+    while (v < n) v <<= 1;
+    return v;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+uint64_t bits(double d)
+{
+    uint64_t u;
+    std::memcpy(&u, &d, sizeof u);
+    return u;
+}
+
+struct PairKeyHash {
+    size_t operator()(const std::pair<uint64_t, uint64_t> &k) const
+    {
+        return std::hash<uint64_t>()(k.first * 0x9e3779b97f4a7c15ull ^ k.second);
+    }
+};
+
+template <class T>
+sht_status upload(T **dst, const std::vector<T> &src, size_t *acc)
+{
+    *dst = nullptr;
+    if (src.empty()) return SHT_OK;
+    const size_t bytes = src.size() * sizeof(T);
+    if (hipMalloc((void **)dst, bytes) != hipSuccess) {
+        *dst = nullptr;
+        return SHT_ERR_OOM;
+    }
+    if (hipMemcpy(*dst, src.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return SHT_ERR_HIP;
+    *acc += bytes;
+    return SHT_OK;
+}
+
+void free_tables(sht_plan_s *p)
+{
+    void *ptrs[] = {p->d_pairs, p->d_mval, p->d_moff, p->d_mu, p->d_A, p->d_cn,
+                    p->d_minv, p->d_rings, p->d_pool};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    p->d_pairs = nullptr; p->d_mval = nullptr; p->d_moff = nullptr; p->d_mu = nullptr;
+    p->d_A = nullptr; p->d_cn = nullptr; p->d_minv = nullptr; p->d_rings = nullptr;
+    p->d_pool = nullptr;
+}
+
+sht_status check_plan(sht_plan_t p)
+{
+    if (!p) return SHT_ERR_BAD_HANDLE;
+    if (p->magic != sht::kPlanMagic) return SHT_ERR_BAD_HANDLE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return SHT_ERR_HIP;
+    if (dev != p->device) return SHT_ERR_INVALID_ARG;
+    return SHT_OK;
+}
+
+sht_status from_hip(hipError_t e) { return e == hipSuccess ? SHT_OK : SHT_ERR_HIP; }
+
+// Recurrence tables in 80-bit extended precision, rounded once to FP64.
+// For each m: beta_l = sqrt((4 l^2 - 1) / (l^2 - m^2)) (Eq. betaDef),
+// c_m = c_{m+1} = 1, c_l = (beta_l / beta_{l-1}) c_{l-2}, A_l = beta_l c_{l-1} / c_l,
+// A at l = m+1 holds beta_{m+1,m} = sqrt(2m+3) (Eq. pm1m).
+void recurrence_tables(int lmax, const std::vector<int32_t> &mval,
+                       const std::vector<long long> &moff, std::vector<double> &A,
+                       std::vector<double> &cn, std::vector<double> &mu)
+{
+    const size_t nalm = (size_t)moff.back();
+    A.assign(nalm, 0.0);
+    cn.assign(nalm, 1.0);
+    std::vector<long double> beta(lmax + 2), c(lmax + 2);
+    for (size_t i = 0; i < mval.size(); ++i) {
+        const int m = mval[i];
+        const long double M = m;
+        const long long off = moff[i];
+        const int len = lmax - m + 1;
+        for (int j = 1; j < len; ++j) {
+            const long double L = m + j;
+            beta[j] = std::sqrt((4.0L * L * L - 1.0L) / (L * L - M * M));
+        }
+        c[0] = 1.0L;
+        if (len > 1) {
+            c[1] = 1.0L;
+            A[off + 1] = (double)beta[1];
+        }
+        for (int j = 2; j < len; ++j) {
+            c[j] = beta[j] / beta[j - 1] * c[j - 2];
+            A[off + j] = (double)(beta[j] * c[j - 1] / c[j]);
+        }
+        for (int j = 0; j < len; ++j) cn[off + j] = (double)c[j];
+    }
+    // mu_m (Eq. pmm) as the running product mu_m = mu_{m-1} sqrt((2m+1)/(2m))
+    const int mmax = mval.back();
+    std::vector<long double> mul(mmax + 1);
+    mul[0] = 1.0L / std::sqrt(4.0L * 3.141592653589793238462643383279502884L);
+    for (int m = 1; m <= mmax; ++m)
+        mul[m] = mul[m - 1] * std::sqrt((2.0L * m + 1.0L) / (2.0L * m));
+    mu.resize(mval.size());
+    for (size_t i = 0; i < mval.size(); ++i) mu[i] = (double)mul[mval[i]];
+}
+
+struct PoolBuilder {
+    std::vector<double2> pool;
+    std::map<long long, long long> unit;  // length -> offset of e^{2 pi i k/len}
+
+    long long roots(long long len)
+    {
+        auto it = unit.find(len);
+        if (it != unit.end()) return it->second;
+        const long long off = (long long)pool.size();
+        pool.resize(pool.size() + len);
+        const long double tp = 2.0L * 3.141592653589793238462643383279502884L;
+        for (long long k = 0; k < len; ++k) {
+            const long double a = tp * (long double)k / (long double)len;
+            pool[off + k] = make_double2((double)std::cos(a), (double)std::sin(a));
+        }
+        unit[len] = off;
+        return off;
+    }
+    long long reserve(long long len)
+    {
+        const long long off = (long long)pool.size();
+        pool.resize(pool.size() + len, make_double2(0.0, 0.0));
+        return off;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *sht_version(void) { return "0.1.0"; }
+
+const char *sht_status_string(sht_status s)
+{
+    switch (s) {
+    case SHT_OK: return "SHT_OK";
+    case SHT_ERR_INVALID_ARG: return "SHT_ERR_INVALID_ARG: invalid argument";
+    case SHT_ERR_OOM: return "SHT_ERR_OOM: allocation failed";
+    case SHT_ERR_HIP: return "SHT_ERR_HIP: HIP runtime error";
+    case SHT_ERR_UNSUPPORTED: return "SHT_ERR_UNSUPPORTED: not supported by this build";
+    case SHT_ERR_BAD_HANDLE: return "SHT_ERR_BAD_HANDLE: invalid plan handle";
+    case SHT_ERR_WORKSPACE: return "SHT_ERR_WORKSPACE: workspace missing or too small";
+    }
+    return "unknown sht_status";
+}
+
+sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
+{
+    if (!out) return SHT_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!d) return SHT_ERR_INVALID_ARG;
+    // ---- validate
+    if (d->lmax < 0 || d->lmax > SHT_MAX_LMAX) return SHT_ERR_INVALID_ARG;
+    if (d->nm < 1 || d->nm > d->lmax + 1) return SHT_ERR_INVALID_ARG;
+    if (d->nrings < 1 || d->nmaps < 1) return SHT_ERR_INVALID_ARG;
+    if (!d->cth || !d->sth || !d->phi0 || !d->nphi) return SHT_ERR_INVALID_ARG;
+    if (d->flags & ~SHT_FLAG_NO_PAIRING) return SHT_ERR_INVALID_ARG;
+    if (d->precision != SHT_FP64) return SHT_ERR_UNSUPPORTED;
+    std::vector<int32_t> mval(d->nm);
+    for (int i = 0; i < d->nm; ++i) {
+        mval[i] = d->mval ? d->mval[i] : i;
+        if (mval[i] < 0 || mval[i] > d->lmax) return SHT_ERR_INVALID_ARG;
+        if (i && mval[i] <= mval[i - 1]) return SHT_ERR_INVALID_ARG;
+    }
+    const int R = d->nrings;
+    std::vector<long long> start(R);
+    long long acc = 0;
+    for (int r = 0; r < R; ++r) {
+        const double x = d->cth[r], s = d->sth[r];
+        if (!(x >= -1.0 && x <= 1.0) || !(s >= 0.0 && s <= 1.0)) return SHT_ERR_INVALID_ARG;
+        if (std::fabs(x * x + s * s - 1.0) > 1e-12) return SHT_ERR_INVALID_ARG;
+        if (!std::isfinite(d->phi0[r])) return SHT_ERR_INVALID_ARG;
+        if (d->nphi[r] < 1) return SHT_ERR_INVALID_ARG;
+        if (d->nphi[r] > SHT_MAX_NPHI) return SHT_ERR_UNSUPPORTED;
+        if (d->ringstart) {
+            if (d->ringstart[r] < 0) return SHT_ERR_INVALID_ARG;
+            start[r] = d->ringstart[r];
+        } else {
+            start[r] = acc;
+            acc += d->nphi[r];
+        }
+    }
+    long long npix = 0;
+    {
+        std::vector<int> ord(R);
+        for (int r = 0; r < R; ++r) ord[r] = r;
+        std::sort(ord.begin(), ord.end(), [&](int a, int b) { return start[a] < start[b]; });
+        for (int t = 0; t < R; ++t) {
+            const int r = ord[t];
+            if (t + 1 < R && start[r] + d->nphi[r] > start[ord[t + 1]]) return SHT_ERR_INVALID_ARG;
+            npix = std::max(npix, start[r] + (long long)d->nphi[r]);
+        }
+    }
+    // ---- Fourier classification per ring
+    std::vector<RingDesc> rings(R);
+    int lds = 1;
+    for (int r = 0; r < R; ++r) {
+        const long long n = d->nphi[r];
+        RingDesc &g = rings[r];
+        std::memset(&g, 0, sizeof g);
+        g.start = start[r];
+        g.phi0 = d->phi0[r];
+        g.n = (int)n;
+        g.clen = (int)((n % 2 == 0) ? n / 2 : n);
+        g.tw = g.tch = g.twb = g.bq = -1;
+        int need;
+        if (smooth7(g.clen) && g.clen <= 8192) {
+            g.nb = 0;
+            need = (n % 2 == 0) ? g.clen + 1 : g.clen;
+        } else if (2LL * g.clen - 1 <= 8192) {
+            g.nb = next_pow2(2LL * g.clen - 1);
+            need = std::max(g.nb, (n % 2 == 0) ? g.clen + 1 : g.clen);
+        } else {
+            return SHT_ERR_UNSUPPORTED;
+        }
+        if (need > kMaxLds) return SHT_ERR_UNSUPPORTED;
+        lds = std::max(lds, need);
+    }
+
+    sht_plan_s *p = new (std::nothrow) sht_plan_s();
+    if (!p) return SHT_ERR_OOM;
+    p->magic = 0;
+    if (hipGetDevice(&p->device) != hipSuccess) { delete p; return SHT_ERR_HIP; }
+    p->lmax = d->lmax;
+    p->nm = d->nm;
+    p->mmax = mval.back();
+    p->nrings = R;
+    p->nmaps = d->nmaps;
+    p->precision = d->precision;
+    p->flags = d->flags;
+    p->npix = npix;
+    p->mval = mval;
+    p->moff.resize(d->nm + 1);
+    p->moff[0] = 0;
+    for (int i = 0; i < d->nm; ++i) p->moff[i + 1] = p->moff[i] + (d->lmax - mval[i] + 1);
+    p->nalm = p->moff.back();
+    p->lds_complex = lds;
+    p->ring_block = 512;
+
+    // ---- pairing of mirror rings (cos negated bitwise, sin equal)
+    std::vector<PairDesc> pairs;
+    {
+        std::vector<char> used(R, 0);
+        std::unordered_map<std::pair<uint64_t, uint64_t>, std::vector<int>, PairKeyHash> south;
+        if (!(d->flags & SHT_FLAG_NO_PAIRING)) {
+            for (int r = R - 1; r >= 0; --r)
+                if (d->cth[r] < 0.0) south[{bits(d->cth[r]), bits(d->sth[r])}].push_back(r);
+            for (int r = 0; r < R; ++r) {
+                if (!(d->cth[r] > 0.0)) continue;
+                auto it = south.find({bits(-d->cth[r]), bits(d->sth[r])});
+                if (it == south.end() || it->second.empty()) continue;
+                const int rs = it->second.back();
+                it->second.pop_back();
+                used[r] = used[rs] = 1;
+                pairs.push_back({d->cth[r], d->sth[r], r, rs});
+            }
+        }
+        for (int r = 0; r < R; ++r)
+            if (!used[r]) pairs.push_back({d->cth[r], d->sth[r], r, -1});
+    }
+    p->npairs = (int)pairs.size();
+
+    std::vector<double> A, cn, mu;
+    recurrence_tables(d->lmax, mval, p->moff, A, cn, mu);
+    std::vector<int32_t> minv(p->mmax + 1, -1);
+    for (int i = 0; i < d->nm; ++i) minv[mval[i]] = i;
+
+    // ---- twiddle / chirp / Bluestein tables
+    PoolBuilder pb;
+    std::vector<int> prep_ids;
+    std::map<int, long long> bq_of_len;
+    for (int r = 0; r < R; ++r) {
+        RingDesc &g = rings[r];
+        g.tw = pb.roots(g.n);
+        if (g.nb) {
+            g.tch = (g.n % 2 == 0) ? g.tw : pb.roots(2LL * g.clen);
+            g.twb = pb.roots(g.nb);
+            auto it = bq_of_len.find(g.clen);
+            if (it == bq_of_len.end()) {
+                g.bq = pb.reserve(g.nb);
+                bq_of_len[g.clen] = g.bq;
+                prep_ids.push_back(r);
+            } else {
+                g.bq = it->second;
+            }
+        }
+    }
+    p->pool_entries = pb.pool.size();
+
+    sht_status st = SHT_OK;
+    size_t tb = 0;
+    if (st == SHT_OK) st = upload(&p->d_pairs, pairs, &tb);
+    if (st == SHT_OK) st = upload(&p->d_mval, mval, &tb);
+    if (st == SHT_OK) st = upload(&p->d_moff, p->moff, &tb);
+    if (st == SHT_OK) st = upload(&p->d_mu, mu, &tb);
+    if (st == SHT_OK) st = upload(&p->d_A, A, &tb);
+    if (st == SHT_OK) st = upload(&p->d_cn, cn, &tb);
+    if (st == SHT_OK) st = upload(&p->d_minv, minv, &tb);
+    if (st == SHT_OK) st = upload(&p->d_rings, rings, &tb);
+    if (st == SHT_OK) st = upload(&p->d_pool, pb.pool, &tb);
+    if (st == SHT_OK && !prep_ids.empty()) {
+        int *d_ids = nullptr;
+        if (hipMalloc((void **)&d_ids, prep_ids.size() * sizeof(int)) != hipSuccess) {
+            st = SHT_ERR_OOM;
+        } else {
+            if (hipMemcpy(d_ids, prep_ids.data(), prep_ids.size() * sizeof(int),
+                          hipMemcpyHostToDevice) != hipSuccess ||
+                sht::launch_bluestein_prep(p, d_ids, (int)prep_ids.size(), nullptr) != hipSuccess ||
+                hipDeviceSynchronize() != hipSuccess)
+                st = SHT_ERR_HIP;
+            (void)hipFree(d_ids);
+        }
+    }
+    if (st != SHT_OK) {
+        free_tables(p);
+        delete p;
+        return st;
+    }
+    p->table_bytes = tb;
+    p->ws_ap_bytes = align_up((size_t)p->nmaps * (size_t)p->nalm * sizeof(double2), 256);
+    p->ws_delta_bytes = align_up((size_t)p->nmaps * (size_t)R * (size_t)p->nm * sizeof(double2), 256);
+    p->magic = sht::kPlanMagic;
+    *out = p;
+    return SHT_OK;
+}
+
+sht_status sht_plan_destroy(sht_plan_t p)
+{
+    if (!p || p->magic != sht::kPlanMagic) return SHT_ERR_BAD_HANDLE;
+    p->magic = sht::kDeadMagic;
+    free_tables(p);
+    delete p;
+    return SHT_OK;
+}
+
+static size_t workspace_bytes(const sht_plan_s *p)
+{
+    const size_t fwd = p->ws_ap_bytes + p->ws_delta_bytes;
+    const size_t adj = p->ws_delta_bytes + align_up(sht::adj_part_bytes(p), 256);
+    return std::max(fwd, adj);
+}
+
+sht_status sht_plan_workspace_size(sht_plan_t p, size_t *bytes)
+{
+    if (!p || p->magic != sht::kPlanMagic) return SHT_ERR_BAD_HANDLE;
+    if (!bytes) return SHT_ERR_INVALID_ARG;
+    *bytes = workspace_bytes(p);
+    return SHT_OK;
+}
+
+sht_status sht_plan_get_info(sht_plan_t p, sht_plan_info *info)
+{
+    if (!p || p->magic != sht::kPlanMagic) return SHT_ERR_BAD_HANDLE;
+    if (!info) return SHT_ERR_INVALID_ARG;
+    info->nalm = p->nalm;
+    info->npix = p->npix;
+    info->nrings = p->nrings;
+    info->npairs = p->npairs;
+    info->nm = p->nm;
+    info->lmax = p->lmax;
+    info->mmax = p->mmax;
+    info->nmaps = p->nmaps;
+    info->workspace_bytes = workspace_bytes(p);
+    info->delta_bytes = (size_t)p->nmaps * (size_t)p->nrings * (size_t)p->nm * sizeof(double2);
+    info->table_bytes = p->table_bytes;
+    return SHT_OK;
+}
+
+sht_status sht_alm2delta(sht_plan_t p, const double *alm, double *delta, void *ws,
+                         size_t ws_bytes, void *stream)
+{
+    sht_status s = check_plan(p);
+    if (s != SHT_OK) return s;
+    if (!alm || !delta) return SHT_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < p->ws_ap_bytes) return SHT_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    double2 *ap = (double2 *)ws;
+    s = from_hip(sht::launch_prescale(p, alm, ap, st));
+    if (s != SHT_OK) return s;
+    return from_hip(sht::launch_legendre_fwd(p, ap, (double2 *)delta, st));
+}
+
+sht_status sht_delta2map(sht_plan_t p, const double *delta, double *map, void *stream)
+{
+    sht_status s = check_plan(p);
+    if (s != SHT_OK) return s;
+    if (!delta || !map) return SHT_ERR_INVALID_ARG;
+    return from_hip(sht::launch_ring_synth(p, (const double2 *)delta, map, (hipStream_t)stream));
+}
+
+sht_status sht_alm2map(sht_plan_t p, const double *alm, double *map, void *ws, size_t ws_bytes,
+                       void *stream)
+{
+    sht_status s = check_plan(p);
+    if (s != SHT_OK) return s;
+    if (!alm || !map) return SHT_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < workspace_bytes(p)) return SHT_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    double2 *ap = (double2 *)ws;
+    double2 *delta = (double2 *)((char *)ws + p->ws_ap_bytes);
+    s = from_hip(sht::launch_prescale(p, alm, ap, st));
+    if (s == SHT_OK) s = from_hip(sht::launch_legendre_fwd(p, ap, delta, st));
+    if (s == SHT_OK) s = from_hip(sht::launch_ring_synth(p, delta, map, st));
+    return s;
+}
+
+sht_status sht_alm2map_events(sht_plan_t p, const double *alm, double *map, void *ws,
+                              size_t ws_bytes, void *stream, void *const *events)
+{
+    sht_status s = check_plan(p);
+    if (s != SHT_OK) return s;
+    if (!alm || !map || !events) return SHT_ERR_INVALID_ARG;
+    for (int k = 0; k < 4; ++k)
+        if (!events[k]) return SHT_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < workspace_bytes(p)) return SHT_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    double2 *ap = (double2 *)ws;
+    double2 *delta = (double2 *)((char *)ws + p->ws_ap_bytes);
+    s = from_hip(hipEventRecord((hipEvent_t)events[0], st));
+    if (s == SHT_OK) s = from_hip(sht::launch_prescale(p, alm, ap, st));
+    if (s == SHT_OK) s = from_hip(hipEventRecord((hipEvent_t)events[1], st));
+    if (s == SHT_OK) s = from_hip(sht::launch_legendre_fwd(p, ap, delta, st));
+    if (s == SHT_OK) s = from_hip(hipEventRecord((hipEvent_t)events[2], st));
+    if (s == SHT_OK) s = from_hip(sht::launch_ring_synth(p, delta, map, st));
+    if (s == SHT_OK) s = from_hip(hipEventRecord((hipEvent_t)events[3], st));
+    return s;
+}
+
+sht_status sht_map2delta_adjoint(sht_plan_t p, const double *map, double *delta, void *stream)
+{
+    sht_status s = check_plan(p);
+    if (s != SHT_OK) return s;
+    if (!delta || !map) return SHT_ERR_INVALID_ARG;
+    return from_hip(sht::launch_ring_anal(p, map, (double2 *)delta, (hipStream_t)stream));
+}
+
+sht_status sht_delta2alm_adjoint(sht_plan_t p, const double *delta, double *alm, void *ws,
+                                 size_t ws_bytes, void *stream)
+{
+    sht_status s = check_plan(p);
+    if (s != SHT_OK) return s;
+    if (!delta || !alm) return SHT_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < sht::adj_part_bytes(p)) return SHT_ERR_WORKSPACE;
+    return from_hip(sht::launch_legendre_adj_ws(p, (const double2 *)delta, (double2 *)ws, alm,
+                                                (hipStream_t)stream));
+}
+
+sht_status sht_alm2map_adjoint(sht_plan_t p, const double *map, double *alm, void *ws,
+                               size_t ws_bytes, void *stream)
+{
+    sht_status s = check_plan(p);
+    if (s != SHT_OK) return s;
+    if (!alm || !map) return SHT_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < workspace_bytes(p)) return SHT_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    double2 *dt = (double2 *)ws;
+    double2 *part = (double2 *)((char *)ws + p->ws_delta_bytes);
+    s = from_hip(sht::launch_ring_anal(p, map, dt, st));
+    if (s == SHT_OK) s = from_hip(sht::launch_legendre_adj_ws(p, dt, part, alm, st));
+    return s;
+}
+
+}  // extern "C"

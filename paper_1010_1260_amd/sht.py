@@ -1,0 +1,208 @@
+"""PyTorch-facing wrapper of the C ABI: plans, device buffers, streams, autograd.
+
+PyTorch provides device memory and the current HIP stream; every step of the
+transform runs in the library's kernels (see include/sht.h).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _cur_stream(dev: torch.device) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A transform plan for one ring geometry, band limit and m-set.
+
+    geom: any object with numpy arrays cth, sth, phi0, nphi, ringstart
+    (e.g. ``workloads.healpix_geometry``).  The plan's tables live on
+    ``device`` (default: the current CUDA/HIP device).
+    """
+
+    def __init__(self, lmax: int, geom, mval=None, nmaps: int = 1, pairing: bool = True,
+                 device=None):
+        lib = L.load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        self.lmax = int(lmax)
+        self.mval = (np.arange(self.lmax + 1, dtype=np.int32) if mval is None
+                     else np.ascontiguousarray(mval, dtype=np.int32))
+        self.nmaps = int(nmaps)
+        self._cth = np.ascontiguousarray(geom.cth, dtype=np.float64)
+        self._sth = np.ascontiguousarray(geom.sth, dtype=np.float64)
+        self._phi0 = np.ascontiguousarray(geom.phi0, dtype=np.float64)
+        self._nphi = np.ascontiguousarray(geom.nphi, dtype=np.int64)
+        rs = getattr(geom, "ringstart", None)
+        self._start = None if rs is None else np.ascontiguousarray(rs, dtype=np.int64)
+        d = L.GeometryDesc()
+        d.lmax = self.lmax
+        d.nm = len(self.mval)
+        d.mval = self.mval.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.nrings = len(self._cth)
+        d.cth = self._cth.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.sth = self._sth.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.phi0 = self._phi0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.nphi = self._nphi.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        d.ringstart = (None if self._start is None
+                       else self._start.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        d.nmaps = self.nmaps
+        d.precision = L.SHT_FP64
+        d.flags = 0 if pairing else L.SHT_FLAG_NO_PAIRING
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(lib.sht_plan(ctypes.byref(h), ctypes.byref(d)), "sht_plan")
+        self._h = h
+        info = L.PlanInfo()
+        L.check(lib.sht_plan_get_info(h, ctypes.byref(info)), "sht_plan_get_info")
+        self.info = info
+        self.nalm = int(info.nalm)
+        self.npix = int(info.npix)
+        self.nrings = int(info.nrings)
+        self.nm = int(info.nm)
+        self.npairs = int(info.npairs)
+        covered = int(np.sum(self._nphi))
+        self._full_cover = covered == self.npix
+        self._ws = None
+
+    # ----------------------------------------------------------------- misc
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.load().sht_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.info.workspace_bytes)
+
+    def workspace(self) -> torch.Tensor:
+        if self._ws is None:
+            self._ws = torch.empty(max(1, self.workspace_bytes), dtype=torch.uint8,
+                                   device=self.device)
+        return self._ws
+
+    def _alm_in(self, alm: torch.Tensor) -> torch.Tensor:
+        if alm.dtype != torch.complex128:
+            raise TypeError("alm must be complex128")
+        if alm.device != self.device:
+            raise ValueError("alm must be on the plan's device")
+        a = alm.reshape(self.nmaps, self.nalm) if alm.dim() == 1 and self.nmaps == 1 else alm
+        if tuple(a.shape) != (self.nmaps, self.nalm):
+            raise ValueError(f"alm must have shape ({self.nmaps}, {self.nalm})")
+        return a.contiguous()
+
+    def _map_in(self, m: torch.Tensor) -> torch.Tensor:
+        if m.dtype != torch.float64:
+            raise TypeError("map must be float64")
+        if m.device != self.device:
+            raise ValueError("map must be on the plan's device")
+        mm = m.reshape(self.nmaps, self.npix) if m.dim() == 1 and self.nmaps == 1 else m
+        if tuple(mm.shape) != (self.nmaps, self.npix):
+            raise ValueError(f"map must have shape ({self.nmaps}, {self.npix})")
+        return mm.contiguous()
+
+    def _new_map(self) -> torch.Tensor:
+        f = torch.empty if self._full_cover else torch.zeros
+        return f((self.nmaps, self.npix), dtype=torch.float64, device=self.device)
+
+    # ---------------------------------------------------------- transforms
+    def alm2map(self, alm: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        a = self._alm_in(alm)
+        out = self._new_map() if out is None else out
+        ws = self.workspace()
+        L.check(L.load().sht_alm2map(self._h, _ptr(a), _ptr(out), _ptr(ws), ws.numel(),
+                                     ctypes.c_void_p(_cur_stream(self.device))), "sht_alm2map")
+        return out
+
+    def alm2map_adjoint(self, m: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        mm = self._map_in(m)
+        out = torch.empty((self.nmaps, self.nalm), dtype=torch.complex128,
+                          device=self.device) if out is None else out
+        ws = self.workspace()
+        L.check(L.load().sht_alm2map_adjoint(self._h, _ptr(mm), _ptr(out), _ptr(ws), ws.numel(),
+                                             ctypes.c_void_p(_cur_stream(self.device))),
+                "sht_alm2map_adjoint")
+        return out
+
+    def alm2delta(self, alm: torch.Tensor) -> torch.Tensor:
+        a = self._alm_in(alm)
+        out = torch.empty((self.nmaps, self.nrings, self.nm), dtype=torch.complex128,
+                          device=self.device)
+        ws = self.workspace()
+        L.check(L.load().sht_alm2delta(self._h, _ptr(a), _ptr(out), _ptr(ws), ws.numel(),
+                                       ctypes.c_void_p(_cur_stream(self.device))),
+                "sht_alm2delta")
+        return out
+
+    def delta2map(self, delta: torch.Tensor) -> torch.Tensor:
+        if delta.dtype != torch.complex128 or tuple(delta.shape) != (self.nmaps, self.nrings,
+                                                                     self.nm):
+            raise ValueError("delta must be complex128 (nmaps, nrings, nm)")
+        dl = delta.contiguous()
+        out = self._new_map()
+        L.check(L.load().sht_delta2map(self._h, _ptr(dl), _ptr(out),
+                                       ctypes.c_void_p(_cur_stream(self.device))),
+                "sht_delta2map")
+        return out
+
+    def map2delta_adjoint(self, m: torch.Tensor) -> torch.Tensor:
+        mm = self._map_in(m)
+        out = torch.empty((self.nmaps, self.nrings, self.nm), dtype=torch.complex128,
+                          device=self.device)
+        L.check(L.load().sht_map2delta_adjoint(self._h, _ptr(mm), _ptr(out),
+                                               ctypes.c_void_p(_cur_stream(self.device))),
+                "sht_map2delta_adjoint")
+        return out
+
+    def delta2alm_adjoint(self, delta: torch.Tensor) -> torch.Tensor:
+        dl = delta.contiguous()
+        out = torch.empty((self.nmaps, self.nalm), dtype=torch.complex128, device=self.device)
+        ws = self.workspace()
+        L.check(L.load().sht_delta2alm_adjoint(self._h, _ptr(dl), _ptr(out), _ptr(ws),
+                                               ws.numel(),
+                                               ctypes.c_void_p(_cur_stream(self.device))),
+                "sht_delta2alm_adjoint")
+        return out
+
+
+class AlmToMap(torch.autograd.Function):
+    """map = alm2map(alm); backward applies the hand-written adjoint.
+
+    The gradient with respect to a complex coefficient is
+    dL/dRe(a) + i dL/dIm(a) (PyTorch's convention for real losses); the
+    imaginary part of a_l0 does not enter the map, so its gradient is 0.
+    """
+
+    @staticmethod
+    def forward(ctx, alm, plan):
+        ctx.plan = plan
+        return plan.alm2map(alm)
+
+    @staticmethod
+    def backward(ctx, grad_map):
+        return ctx.plan.alm2map_adjoint(grad_map.contiguous()).reshape(
+            ctx.plan.nmaps, ctx.plan.nalm), None
+
+
+def alm2map(alm: torch.Tensor, plan: Plan) -> torch.Tensor:
+    """Differentiable alm2map (autograd through AlmToMap)."""
+    return AlmToMap.apply(alm, plan)
