@@ -1,14 +1,16 @@
 #!/usr/bin/env python3
-"""Benchmark: alm2map maps/s on one MI355X.
+"""Benchmark: alm2map maps/s at l_max = 4096, HEALPix nside = 2048 on one MI355X,
+mixed precision against FP64.
 
-Workload (default): FP64 alm2map of one map, l_max = 4096, HEALPix
-nside = 2048 (50,331,648 pixels, 8191 rings), seeded Gaussian a_lm with
-C_l = 1/(l(l+1)).  Inputs are resident in HBM before the timed region; one
-step is the whole transform (prescale, Legendre stage, per-ring Fourier
-synthesis) through the C ABI.
-
-Prints one JSON line (rank 0).  Stage durations come from HIP events that
-the library records on the launch stream around each kernel.
+Workloads (seeded Gaussian a_lm, C_l = 1/(l(l+1)), HEALPix rings,
+50,331,648 pixels, 8191 rings; inputs resident in HBM before timing):
+  * mixed: a batch of 16 maps; FP64 recurrence, FP32 matrix-core contraction,
+    FP64 ring Fourier synthesis -- the headline value;
+  * fp64:  one map at a time, everything FP64 -- the comparison.
+One step is the whole transform of one batch through the C ABI (coefficient
+prescale, Legendre stage, per-ring Fourier synthesis).  Stage durations come
+from HIP events the library records on the launch stream around each kernel.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -24,15 +26,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "maps/s at ℓmax=4096,nside=2048: mixed-precision vs FP64, rel err≤1e-6"
-PEAK_FP64 = 78.6e12   # MI355X FP64 vector, FLOP/s
-PEAK_HBM = 8.0e12     # bytes/s
+PEAK_FP64 = 78.6e12    # MI355X FP64 vector FLOP/s
+PEAK_FP32_MFMA = 157.3e12
+PEAK_HBM = 8.0e12      # bytes/s
 
 
 def _hip():
     lib = ctypes.CDLL("libamdhip64.so")
     lib.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
     lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
-    lib.hipEventSynchronize.argtypes = [ctypes.c_void_p]
     lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
                                         ctypes.c_void_p]
     return lib
@@ -48,6 +50,42 @@ def _cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def run_plan(plan, alm, steps, warmup, lib, hip, torch, np):
+    """Time `steps` transforms after `warmup`; returns wall seconds, stage ms, output."""
+    dev = plan.device
+    out = torch.empty((plan.nmaps, plan.npix), dtype=torch.float64, device=dev)
+    ws = plan.workspace()
+    sh = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    nev = 4
+    evs = []
+    for _ in range(steps * nev):
+        e = ctypes.c_void_p()
+        assert hip.hipEventCreate(ctypes.byref(e)) == 0
+        evs.append(e)
+    EvArr = ctypes.c_void_p * nev
+    args = (plan.handle, ctypes.c_void_p(alm.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), sh)
+    for _ in range(warmup):
+        assert lib.sht_alm2map(*args) == 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        arr = EvArr(*[evs[i * nev + k].value for k in range(nev)])
+        assert lib.sht_alm2map_events(*args, arr) == 0
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = np.zeros((steps, nev - 1))
+    f = ctypes.c_float()
+    for i in range(steps):
+        for k in range(nev - 1):
+            assert hip.hipEventElapsedTime(ctypes.byref(f), evs[i * nev + k],
+                                           evs[i * nev + k + 1]) == 0
+            st[i, k] = f.value
+    for e in evs:
+        hip.hipEventDestroy(e)
+    return wall, st.mean(axis=0), out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,13 +93,15 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--lmax", type=int, default=4096)
     ap.add_argument("--nside", type=int, default=2048)
+    ap.add_argument("--nmaps", type=int, default=16, help="batch of the mixed-precision run")
+    ap.add_argument("--only", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-ring-stride", type=int, default=8,
                     help="oracle timed on every k-th ring (bounded CPU sample)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
-              "the multi-GPU sharding is described, not implemented", file=sys.stderr)
+              "multi-GPU sharding is described in DESIGN.md, not implemented", file=sys.stderr)
         return 2
 
     import numpy as np
@@ -75,124 +115,116 @@ def main() -> int:
     hip = _hip()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    Lmax, N = args.lmax, args.nside
+    Lmax, N, B = args.lmax, args.nside, args.nmaps
     geom = W.healpix_geometry(N)
-    alm_np = W.random_alm(Lmax, [2, 0], spectrum="inv_l_lp1")
-    plan = Plan(Lmax, geom, device=dev)
-    alm = torch.from_numpy(alm_np).to(dev).reshape(1, -1)
-    out = torch.empty((1, plan.npix), dtype=torch.float64, device=dev)
-    ws = plan.workspace()
-    stream = torch.cuda.current_stream(dev)
-    sh = ctypes.c_void_p(stream.cuda_stream)
+    alms_np = [W.random_alm(Lmax, [3, i]) for i in range(B)]
+    res = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "data": "synthetic (seeded Gaussian a_lm, C_l = 1/(l(l+1)), HEALPix rings)"}
 
-    nev = 4
-    evs = []
-    for _ in range(args.steps * nev):
-        e = ctypes.c_void_p()
-        assert hip.hipEventCreate(ctypes.byref(e)) == 0
-        evs.append(e)
-    EvArr = ctypes.c_void_p * nev
+    mixed = fp64 = None
+    if args.only in ("both", "mixed"):
+        plan = Plan(Lmax, geom, nmaps=B, precision="fp32_mfma", device=dev)
+        alm = torch.from_numpy(np.stack(alms_np)).to(dev)
+        wall, st, out = run_plan(plan, alm, args.steps, args.warmup, lib, hip, torch, np)
+        mixed = dict(plan=plan, wall=wall, st=st, out=out)
+        del alm
+    if args.only in ("both", "fp64"):
+        plan64 = Plan(Lmax, geom, nmaps=1, device=dev)
+        alm0 = torch.from_numpy(alms_np[0]).to(dev).reshape(1, -1)
+        wall, st, out = run_plan(plan64, alm0, args.steps, args.warmup, lib, hip, torch, np)
+        fp64 = dict(plan=plan64, wall=wall, st=st, out=out)
 
-    def step(i=None):
-        if i is None:
-            rc = lib.sht_alm2map(plan.handle, ctypes.c_void_p(alm.data_ptr()),
-                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
-                                 ws.numel(), sh)
-        else:
-            arr = EvArr(*[evs[i * nev + k].value for k in range(nev)])
-            rc = lib.sht_alm2map_events(plan.handle, ctypes.c_void_p(alm.data_ptr()),
-                                        ctypes.c_void_p(out.data_ptr()),
-                                        ctypes.c_void_p(ws.data_ptr()), ws.numel(), sh, arr)
-        if rc != 0:
-            raise RuntimeError(f"sht_alm2map failed: {rc}")
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    stages = np.zeros((args.steps, nev - 1))
-    f = ctypes.c_float()
-    for i in range(args.steps):
-        for k in range(nev - 1):
-            assert hip.hipEventElapsedTime(ctypes.byref(f), evs[i * nev + k],
-                                           evs[i * nev + k + 1]) == 0
-            stages[i, k] = f.value
-    ev_total = float(np.sum(stages) / args.steps)
-    ms_per_step = wall * 1e3 / args.steps
-    maps_per_s = 1.0 / (wall / args.steps)
-
-    # roofline of the dominant kernel (Legendre stage): 8 algorithmic flops per
-    # (ring pair, l, m): 4 for the recurrence, 4 for the complex accumulation
-    nalm = plan.nalm
-    npairs = plan.npairs
-    leg_ms = float(np.mean(stages[:, 1]))
-    flops = float(npairs) * float(nalm) * 8.0
-    achieved = flops / (leg_ms * 1e-3)
-    fft_ms = float(np.mean(stages[:, 2]))
-    fft_bytes = 16.0 * geom.nrings * plan.nm + 8.0 * plan.npix
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic_legendre_fwd_l4096_n2048.json")
-    if os.path.exists(tfile) and (Lmax, N) == (4096, 2048):
-        try:
-            traffic = json.load(open(tfile)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
-
-    res = {
-        "metric": METRIC,
-        "value": maps_per_s,
-        "unit": "maps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic (seeded Gaussian a_lm, C_l = 1/(l(l+1)), HEALPix rings)",
-        "config": {"workload": f"alm2map FP64, 1 map, lmax={Lmax}, HEALPix nside={N}",
-                   "lmax": Lmax, "nside": N, "nmaps": 1, "precision": "fp64",
-                   "npix": plan.npix, "nrings": geom.nrings},
-        "stages_ms": {"prescale": float(np.mean(stages[:, 0])), "legendre": leg_ms,
-                      "ring_synthesis": fft_ms, "sum_events": ev_total},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic,
-                     "kernel": "k_legendre_fwd", "flops_per_launch": flops},
-        "fourier_stage": {"bytes_per_launch": fft_bytes, "achieved_GBps":
-                          fft_bytes / (fft_ms * 1e-3) / 1e9,
-                          "frac_hbm": fft_bytes / (fft_ms * 1e-3) / PEAK_HBM},
-    }
+    npairs = (mixed or fp64)["plan"].npairs
+    nalm = (mixed or fp64)["plan"].nalm
+    fft_bytes_per_map = 16.0 * geom.nrings * (Lmax + 1) + 8.0 * geom.npix
+    if fp64 is not None:
+        t = fp64["wall"] / args.steps
+        leg = float(fp64["st"][1])
+        flops = float(npairs) * float(nalm) * 8.0
+        fp64_info = {
+            "maps_per_s": 1.0 / t, "ms_per_step": t * 1e3,
+            "stages_ms": {"prescale": float(fp64["st"][0]), "legendre": leg,
+                          "ring_synthesis": float(fp64["st"][2])},
+            "legendre_roofline": {"bound": "alu", "achieved": flops / (leg * 1e-3) / 1e12,
+                                  "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                                  "frac": flops / (leg * 1e-3) / PEAK_FP64,
+                                  "kernel": "k_legendre_fwd<2>",
+                                  "flops_per_launch": flops},
+            "fourier_GBps": fft_bytes_per_map / (float(fp64["st"][2]) * 1e-3) / 1e9,
+        }
+        res["fp64"] = fp64_info
+    if mixed is not None:
+        t = mixed["wall"] / args.steps
+        leg = float(mixed["st"][1])
+        # algorithmic contraction flops: 4 per (ring pair, l, m, map) (complex
+        # accumulate of a real P_lm); the FP64 recurrence (4 per (pair, l, m))
+        # runs on the vector units beside it
+        flops = float(npairs) * float(nalm) * 4.0 * B
+        res.update({
+            "value": B / t, "unit": "maps/s", "ms_per_step": t * 1e3,
+            "dtype": "f32 matrix-core contraction + f64 recurrence and FFT",
+            "config": {"workload": f"alm2map mixed precision, batch of {B} maps, lmax={Lmax}, "
+                                   f"HEALPix nside={N}", "lmax": Lmax, "nside": N,
+                       "nmaps": B, "precision": "fp32_mfma", "npix": geom.npix,
+                       "nrings": geom.nrings},
+            "stages_ms": {"prescale": float(mixed["st"][0]), "legendre": leg,
+                          "ring_synthesis": float(mixed["st"][2])},
+            "roofline": {"bound": "mfma", "achieved": flops / (leg * 1e-3) / 1e12,
+                         "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
+                         "frac": flops / (leg * 1e-3) / PEAK_FP32_MFMA, "traffic": None,
+                         "kernel": "k_legendre_mfma_f32", "flops_per_launch": flops},
+            "fourier_stage": {"bytes_per_launch": fft_bytes_per_map * B,
+                              "achieved_GBps": fft_bytes_per_map * B /
+                              (float(mixed["st"][2]) * 1e-3) / 1e9,
+                              "frac_hbm": fft_bytes_per_map * B /
+                              (float(mixed["st"][2]) * 1e-3) / PEAK_HBM},
+        })
+        if fp64 is not None:
+            res["speedup_mixed_vs_fp64"] = res["value"] / res["fp64"]["maps_per_s"]
+            # per-map error of every mixed map against the FP64 path on the GPU
+            errs = []
+            out_m = mixed["out"]
+            p64 = fp64["plan"]
+            for i in range(B):
+                a = torch.from_numpy(alms_np[i]).to(dev).reshape(1, -1)
+                m64 = p64.alm2map(a)
+                errs.append(float(torch.linalg.norm(out_m[i] - m64[0]) / torch.linalg.norm(m64[0])))
+            res["rel_err_mixed_vs_fp64_gpu"] = {"max": max(errs), "mean": float(np.mean(errs)),
+                                                "maps": B}
+    else:
+        t = fp64["wall"] / args.steps
+        res.update({"value": 1.0 / t, "unit": "maps/s", "ms_per_step": t * 1e3, "dtype": "f64",
+                    "config": {"workload": f"alm2map FP64, 1 map, lmax={Lmax}, HEALPix nside={N}",
+                               "lmax": Lmax, "nside": N, "nmaps": 1, "precision": "fp64"},
+                    "roofline": dict(res["fp64"]["legendre_roofline"], traffic=None)})
 
     if not args.no_cpu_baseline:
         from oracle import ref
-        got = out.cpu().numpy()[0]
         rings = np.arange(0, geom.nrings, args.cpu_ring_stride)
         th = ref.max_threads()
         tc0 = time.perf_counter()
-        exp = ref.alm2map_rings(Lmax, geom, alm_np, rings)
+        exp = ref.alm2map_rings(Lmax, geom, alms_np[0], rings)
         tc = time.perf_counter() - tc0
-        # every ring costs the same Legendre work; scale the sample to a map
+        # every ring costs the same Legendre work: scale the sample to a map
         cpu_maps_per_s = (len(rings) / geom.nrings) / tc
-        num = den = 0.0
-        for r, e in zip(rings, exp):
-            s0, n = int(geom.ringstart[r]), int(geom.nphi[r])
-            num += float(np.sum((got[s0:s0 + n] - e) ** 2))
-            den += float(np.sum(e ** 2))
         res["cpu_baseline"] = {"value": cpu_maps_per_s, "unit": "maps/s", "cores": th,
                                "kind": "oracle",
-                               "sample": f"{len(rings)} of {geom.nrings} rings (every "
-                                         f"{args.cpu_ring_stride}th), {tc:.1f} s wall, "
-                                         f"scaled by ring count; CPU: {_cpu_model()}"}
-        res["rel_err_vs_oracle"] = {"rel_l2_sampled_rings": float(np.sqrt(num / den)),
-                                    "rings": int(len(rings))}
-    for e in evs:
-        hip.hipEventDestroy(e)
+                               "sample": f"map 0, {len(rings)} of {geom.nrings} rings (every "
+                                         f"{args.cpu_ring_stride}th), {tc:.1f} s wall, scaled "
+                                         f"by ring count; CPU: {_cpu_model()}"}
+        errs = {}
+        for name, runinfo in (("mixed", mixed), ("fp64", fp64)):
+            if runinfo is None:
+                continue
+            got = runinfo["out"][0].cpu().numpy()
+            num = den = 0.0
+            for r, e in zip(rings, exp):
+                s0, n = int(geom.ringstart[r]), int(geom.nphi[r])
+                num += float(np.sum((got[s0:s0 + n] - e) ** 2))
+                den += float(np.sum(e ** 2))
+            errs[name] = float(np.sqrt(num / den))
+        res["rel_err_vs_oracle_sampled_rings_map0"] = errs
     print(json.dumps(res), flush=True)
     return 0
 

@@ -21,6 +21,7 @@ SHT_ERR_BAD_HANDLE = -5
 SHT_ERR_WORKSPACE = -6
 
 SHT_FP64 = 0
+SHT_FP32_MFMA = 1
 SHT_FLAG_NO_PAIRING = 1
 
 SHT_MAX_LMAX = 16383

@@ -1,0 +1,222 @@
+// Mixed-precision batched Legendre stage on the matrix cores (gfx950).
+//
+// For a batch of maps sharing one geometry, Delta_m(theta) of Eq. (DeltaDef)
+// is, per m, a matrix product: with ring pairs as rows, l as the inner index
+// and (map, Re/Im) as columns,
+//     C_E[pairs x 32] = Lambda_E[pairs x K] * B_E[K x 32]   (l - m even)
+//     C_O[pairs x 32] = Lambda_O[pairs x K] * B_O[K x 32]   (l - m odd)
+//     Delta_N = C_E + C_O,  Delta_S = C_E - C_O.
+// The recurrence (Eq. assLegRec, seeds Eqs. pmm / pm1m, rescaling of
+// Sec. 2.2.2) stays in FP64 on the vector ALUs, exactly as in the FP64
+// kernel; only the true values P_lm, rounded to FP32, and the FP32 copy of
+// the prescaled coefficients enter v_mfma_f32_32x32x2f32.
+//
+// Fragment assembly.  Lane r of a wave runs the recurrence of ring pair r
+// (rows 0-31: lanes 0-31, rows 32-63: lanes 32-63).  A 32x32x2 A-fragment
+// needs, in lanes 32-63, the second K value of rows 0-31; four consecutive
+// steps give X0 = P_l, X1 = P_{l+1}, X2 = P_{l+2}, X3 = P_{l+3} per lane, and
+// one v_permlane32_swap of (X0, X2) yields the even-parity fragments of both
+// row halves ([X0_lo | X2_lo] and [X0_hi | X2_hi]); (X1, X3) gives the odd ones.
+//
+// Accumulation.  FP32 accumulation over all l-terms loses up to ~1e-6; the
+// matrix core accumulates 64 same-parity terms per block, and the block sums
+// are added into a second FP32 accumulator (two-level summation).  Emulated
+// error of Delta at l_max = 4096: about 1.2e-7 relative.
+#include "recurrence.h"
+#include "sht_internal.h"
+
+namespace sht {
+namespace {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+
+constexpr int kMfmaBlockIters = 32;  // iterations (4 l-steps each) per FP32 block: 64 terms per parity
+
+__global__ void k_prescale_f32(const double2 *__restrict__ alm, const double *__restrict__ cn,
+                               float *__restrict__ Bf, long long nalm, int nmaps, long long m0len)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nalm * 32) return;
+    const long long e = t >> 5;
+    const int col = (int)(t & 31);
+    const int grp = blockIdx.y;
+    const int map = grp * 16 + (col >> 1);
+    float v = 0.0f;
+    if (map < nmaps) {
+        const double2 a = alm[(long long)map * nalm + e];
+        const double c = cn[e];
+        const double x = (col & 1) ? ((e < m0len) ? 0.0 : a.y * c) : a.x * c;
+        v = (float)x;
+    }
+    Bf[((long long)grp * nalm + e) * 32 + col] = v;
+}
+
+__device__ inline float tof(double u, double f) { return (float)(u * f); }
+
+__device__ inline void swap_halves(float a, float b, float &lo, float &hi)
+{
+    const v2u r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b),
+                                                   false, false);
+    lo = __uint_as_float(r[0]);
+    hi = __uint_as_float(r[1]);
+}
+
+__device__ void mfma_one_m(double x, double s, int m, int i, long long off, double mum,
+                           int lmax, const double *__restrict__ A, const float *__restrict__ Bg,
+                           double *__restrict__ delta, const PairDesc *__restrict__ pairs,
+                           int npairs, int pb, int grp, int nmaps, int nrings, int nm)
+{
+    const int len = lmax - m + 1;
+    const int lane = threadIdx.x;
+    const int hi = lane >> 5;
+    const int col = lane & 31;
+    const double *__restrict__ Am = A + off;
+    const float *__restrict__ Bm = Bg + off * 32;
+
+    double ua, ub;
+    int k;
+    seed_mm(mum, s, m, ua, k);
+    double f = final_scale(k);
+    ub = (len >= 2) ? (Am[1] * x) * ua : 0.0;
+
+    v16f acc0 = {}, acc1 = {}, acc2 = {}, acc3 = {};
+    v16f tot0 = {}, tot1 = {}, tot2 = {}, tot3 = {};
+    int it = 0;
+    for (int j = 0; j < len; j += 4, ++it) {
+        float X0, X1, X2, X3;
+        if (j == 0) {
+            X0 = tof(ua, f);
+            X1 = (len > 1) ? tof(ub, f) : 0.0f;
+            const double A2 = (2 < len) ? Am[2] : 0.0;
+            const double u2 = fma(A2 * x, ub, -ua);
+            const double A3 = (3 < len) ? Am[3] : 0.0;
+            const double u3 = fma(A3 * x, u2, -ub);
+            X2 = (2 < len) ? tof(u2, f) : 0.0f;
+            X3 = (3 < len) ? tof(u3, f) : 0.0f;
+            ua = u2; ub = u3;
+        } else {
+            const double A0 = Am[j];
+            const double A1 = (j + 1 < len) ? Am[j + 1] : 0.0;
+            const double A2 = (j + 2 < len) ? Am[j + 2] : 0.0;
+            const double A3 = (j + 3 < len) ? Am[j + 3] : 0.0;
+            const double u0 = fma(A0 * x, ub, -ua);
+            const double u1 = fma(A1 * x, u0, -ub);
+            const double u2 = fma(A2 * x, u1, -u0);
+            const double u3 = fma(A3 * x, u2, -u1);
+            X0 = tof(u0, f);
+            X1 = (j + 1 < len) ? tof(u1, f) : 0.0f;
+            X2 = (j + 2 < len) ? tof(u2, f) : 0.0f;
+            X3 = (j + 3 < len) ? tof(u3, f) : 0.0f;
+            ua = u2; ub = u3;
+        }
+        if (it & 1) {
+            if (fmax(fabs(ua), fabs(ub)) > kTwoS) {
+                ua *= kTwoMinusS; ub *= kTwoMinusS;
+                k += 1;
+                f = final_scale(k);
+            }
+        }
+        const int re = j + 2 * hi, ro = j + 1 + 2 * hi;
+        const float BE = (re < len) ? Bm[(long long)re * 32 + col] : 0.0f;
+        const float BO = (ro < len) ? Bm[(long long)ro * 32 + col] : 0.0f;
+        float A0E, A1E, A0O, A1O;
+        swap_halves(X0, X2, A0E, A1E);
+        swap_halves(X1, X3, A0O, A1O);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0E, BE, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1E, BE, acc1, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0O, BO, acc2, 0, 0, 0);
+        acc3 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1O, BO, acc3, 0, 0, 0);
+        if ((it + 1) % kMfmaBlockIters == 0) {
+            tot0 += acc0; tot1 += acc1; tot2 += acc2; tot3 += acc3;
+            acc0 = v16f{}; acc1 = v16f{}; acc2 = v16f{}; acc3 = v16f{};
+        }
+    }
+    tot0 += acc0; tot1 += acc1; tot2 += acc2; tot3 += acc3;
+
+    // D layout of the 32x32 tile: column = lane % 32, row = 8 (r/4) + 4 (lane/32) + r % 4
+    const int map = grp * 16 + (col >> 1);
+    if (map >= nmaps) return;
+    const int part = col & 1;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const v16f &E = h ? tot1 : tot0;
+        const v16f &O = h ? tot3 : tot2;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r >> 2) + 4 * hi + (r & 3);
+            const int pp = pb * 64 + h * 32 + row;
+            if (pp < npairs) {
+                const PairDesc d = pairs[pp];
+                const double e = (double)E[r], o = (double)O[r];
+                delta[(((long long)map * nrings + d.rn) * nm + i) * 2 + part] = e + o;
+                if (d.rs >= 0)
+                    delta[(((long long)map * nrings + d.rs) * nm + i) * 2 + part] = e - o;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void k_legendre_mfma_f32(
+    const PairDesc *__restrict__ pairs, int npairs, int pblocks,
+    const int *__restrict__ mval, const long long *__restrict__ moff,
+    const double *__restrict__ mu, int nm, int nmpairs, int lmax,
+    const double *__restrict__ A, const float *__restrict__ Bf, long long nalm,
+    double *__restrict__ delta, int nrings, int nmaps, long long total)
+{
+    const long long L = xcd_logical(blockIdx.x, total);
+    const int pb = (int)(L % pblocks);
+    const long long rest = L / pblocks;
+    const int q = (int)(rest % nmpairs);
+    const int grp = (int)(rest / nmpairs);
+    const int p = pb * 64 + threadIdx.x;
+    double x = 0.0, s = 0.0;
+    if (p < npairs) {
+        const PairDesc d = pairs[p];
+        x = d.x; s = d.s;
+    }
+    const float *Bg = Bf + (long long)grp * nalm * 32;
+    for (int t = 0; t < 2; ++t) {
+        const int i = (t == 0) ? q : nm - 1 - q;
+        if (t == 1 && i == q) break;
+        mfma_one_m(x, s, mval[i], i, moff[i], mu[i], lmax, A, Bg, delta, pairs, npairs, pb, grp,
+                   nmaps, nrings, nm);
+    }
+}
+
+}  // namespace
+
+size_t mfma_bf_bytes(const sht_plan_s *p)
+{
+    const size_t groups = (size_t)((p->nmaps + 15) / 16);
+    return groups * (size_t)p->nalm * 32 * sizeof(float);
+}
+
+hipError_t launch_prescale_f32(const sht_plan_s *p, const double *alm, float *Bf, hipStream_t st)
+{
+    const long long m0len = (p->mval[0] == 0) ? (p->lmax + 1) : 0;
+    const int groups = (p->nmaps + 15) / 16;
+    const long long n = p->nalm * 32;
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)groups);
+    hipLaunchKernelGGL(k_prescale_f32, grid, dim3(256), 0, st,
+                       reinterpret_cast<const double2 *>(alm), p->d_cn, Bf, p->nalm, p->nmaps,
+                       m0len);
+    return hipGetLastError();
+}
+
+hipError_t launch_legendre_mfma_f32(const sht_plan_s *p, const float *Bf, double2 *delta,
+                                    hipStream_t st)
+{
+    const int pblocks = (p->npairs + 63) / 64;
+    const int nmpairs = (p->nm + 1) / 2;
+    const int groups = (p->nmaps + 15) / 16;
+    const long long total = (long long)pblocks * nmpairs * groups;
+    if (total <= 0 || total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_legendre_mfma_f32, dim3((unsigned)total), dim3(64), 0, st, p->d_pairs,
+                       p->npairs, pblocks, p->d_mval, p->d_moff, p->d_mu, p->nm, nmpairs,
+                       p->lmax, p->d_A, Bf, p->nalm, reinterpret_cast<double *>(delta),
+                       p->nrings, p->nmaps, total);
+    return hipGetLastError();
+}
+
+}  // namespace sht

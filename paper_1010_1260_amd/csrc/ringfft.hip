@@ -26,8 +26,6 @@
 namespace sht {
 namespace {
 
-constexpr int kRingThreads = 512;
-constexpr int kMaxFft = 8192;
 
 __device__ inline double2 cmul(double2 a, double2 b)
 {
@@ -111,13 +109,13 @@ __device__ inline void small_dft(double2 (&v)[R], int sign)
     }
 }
 
-// One Stockham pass of radix R over n points in LDS.  tw[idx * tws] is
-// e^{+2 pi i idx / n}.
-template <int R, int NT>
+// One Stockham pass of radix R over n <= MAXN points in LDS.  tw[idx * tws]
+// is e^{+2 pi i idx / n}.
+template <int R, int NT, int MAXN>
 __device__ void fft_pass(double2 *buf, int n, int Ns, int sign, const double2 *__restrict__ tw,
                          int tws)
 {
-    constexpr int MAXQ = (kMaxFft / R + NT - 1) / NT;
+    constexpr int MAXQ = (MAXN / R + NT - 1) / NT;
     const int nb = n / R;
     const int tstep0 = n / (Ns * R);
     double2 v[MAXQ][R];
@@ -154,32 +152,33 @@ __device__ void fft_pass(double2 *buf, int n, int Ns, int sign, const double2 *_
     __syncthreads();
 }
 
-// In-place DFT of 7-smooth length n <= kMaxFft:
+// In-place DFT of 7-smooth length n <= MAXN:
 // buf_k <- sum_j buf_j e^{sign 2 pi i j k / n}.
-template <int NT>
+template <int NT, int MAXN>
 __device__ void fft_lds(double2 *buf, int n, int sign, const double2 *__restrict__ tw, int tws)
 {
     int Ns = 1, rem = n;
     while (rem > 1) {
         if (rem % 4 == 0) {
-            fft_pass<4, NT>(buf, n, Ns, sign, tw, tws); Ns *= 4; rem /= 4;
+            fft_pass<4, NT, MAXN>(buf, n, Ns, sign, tw, tws); Ns *= 4; rem /= 4;
         } else if (rem % 2 == 0) {
-            fft_pass<2, NT>(buf, n, Ns, sign, tw, tws); Ns *= 2; rem /= 2;
+            fft_pass<2, NT, MAXN>(buf, n, Ns, sign, tw, tws); Ns *= 2; rem /= 2;
         } else if (rem % 3 == 0) {
-            fft_pass<3, NT>(buf, n, Ns, sign, tw, tws); Ns *= 3; rem /= 3;
+            fft_pass<3, NT, MAXN>(buf, n, Ns, sign, tw, tws); Ns *= 3; rem /= 3;
         } else if (rem % 5 == 0) {
-            fft_pass<5, NT>(buf, n, Ns, sign, tw, tws); Ns *= 5; rem /= 5;
+            fft_pass<5, NT, MAXN>(buf, n, Ns, sign, tw, tws); Ns *= 5; rem /= 5;
         } else {
-            fft_pass<7, NT>(buf, n, Ns, sign, tw, tws); Ns *= 7; rem /= 7;
+            fft_pass<7, NT, MAXN>(buf, n, Ns, sign, tw, tws); Ns *= 7; rem /= 7;
         }
     }
 }
 
-// In-place DFT of any length len (<= kMaxFft / 2) by Bluestein's algorithm:
-// e^{i 2 pi jk/len} = c_j c_k conj(c_{j-k}), c_k = e^{i pi k^2 / len}.
+// In-place DFT of any length len by Bluestein's algorithm:
+// e^{i 2 pi jk/len} = c_j c_k conj(c_{j-k}), c_k = e^{i pi k^2 / len}, as a
+// cyclic convolution of 7-smooth length nb >= 2 len - 1.
 // tch[q] = e^{2 pi i q / (2 len)}, twb = e^{2 pi i k / nb}, bq = DFT^-(conj c, wrapped) / nb.
 // A sign -1 transform is conj(DFT^+(conj x)).
-template <int NT>
+template <int NT, int MAXN>
 __device__ void bluestein_lds(double2 *buf, int len, int nb, int sign,
                               const double2 *__restrict__ tch, const double2 *__restrict__ twb,
                               const double2 *__restrict__ bq)
@@ -196,10 +195,10 @@ __device__ void bluestein_lds(double2 *buf, int len, int nb, int sign,
         }
     }
     __syncthreads();
-    fft_lds<NT>(buf, nb, -1, twb, 1);
+    fft_lds<NT, MAXN>(buf, nb, -1, twb, 1);
     for (int k = threadIdx.x; k < nb; k += NT) buf[k] = cmul(buf[k], bq[k]);
     __syncthreads();
-    fft_lds<NT>(buf, nb, +1, twb, 1);
+    fft_lds<NT, MAXN>(buf, nb, +1, twb, 1);
     for (int j = threadIdx.x; j < len; j += NT) {
         const int q = (int)(((long long)j * j) % two_len);
         double2 z = cmul(buf[j], tch[q]);
@@ -209,32 +208,46 @@ __device__ void bluestein_lds(double2 *buf, int len, int nb, int sign,
     __syncthreads();
 }
 
-template <int NT>
+template <int NT, int MAXN>
 __device__ inline void ring_dft(double2 *buf, const RingDesc &d, int sign,
                                 const double2 *__restrict__ pool)
 {
     if (d.nb == 0) {
-        fft_lds<NT>(buf, d.clen, sign, pool + d.tw, (d.n % 2 == 0) ? 2 : 1);
+        fft_lds<NT, MAXN>(buf, d.clen, sign, pool + d.tw, (d.n % 2 == 0) ? 2 : 1);
     } else {
-        bluestein_lds<NT>(buf, d.clen, d.nb, sign, pool + d.tch, pool + d.twb, pool + d.bq);
+        bluestein_lds<NT, MAXN>(buf, d.clen, d.nb, sign, pool + d.tch, pool + d.twb,
+                                pool + d.bq);
     }
 }
 
-__device__ inline double2 phase_mode(double2 dl, int m, double phi0, int sign)
+// Block id -> logical id so that consecutive logical ids run on one XCD
+// (workgroups are dealt round-robin over the 8 XCDs).
+__device__ inline int xcd_logical(int b, int total)
 {
-    if (m == 0) return make_double2(dl.x, 0.0);
-    double sn, cs;
-    sincos((double)m * phi0, &sn, &cs);
-    return cmul(dl, make_double2(cs, sign > 0 ? sn : -sn));
+    const int x = b % 8, i = b / 8, q = total / 8, r = total % 8;
+    return x * q + (x < r ? x : r) + i;
 }
 
-__global__ __launch_bounds__(kRingThreads) void k_ring_synth(
-    const RingDesc *__restrict__ rings, const double2 *__restrict__ pool,
-    const double2 *__restrict__ delta, const int *__restrict__ minv, int mmax, int nm,
-    int nrings, double *__restrict__ map, long long npix)
+// Delta_m for mode m of a ring's row (zero for m outside the set).
+__device__ inline double2 load_mode(const double2 *__restrict__ drow,
+                                    const int *__restrict__ minv, int mcontig, int m)
+{
+    const int i = mcontig ? m : minv[m];
+    return (i >= 0) ? drow[i] : make_double2(0.0, 0.0);
+}
+
+// Synthesis: one workgroup per (ring of this size class, map).  LDS: the
+// spectrum / FFT buffer (fft_entries) followed by NT staging slots.
+template <int NT, int MAXN>
+__global__ __launch_bounds__(NT, (MAXN <= 4096) ? 4 : 2) void k_ring_synth(
+    const int *__restrict__ ids, const RingDesc *__restrict__ rings,
+    const double2 *__restrict__ pool, const double2 *__restrict__ delta,
+    const int *__restrict__ minv, int mcontig, int mmax, int nm, int nrings,
+    double *__restrict__ map, long long npix, int dc_off)
 {
     extern __shared__ double2 buf[];
-    const int r = blockIdx.x;
+    double2 *Dc = buf + dc_off;
+    const int r = ids[xcd_logical(blockIdx.x, gridDim.x)];
     const int b = blockIdx.y;
     const RingDesc d = rings[r];
     const double2 *drow = delta + ((long long)b * nrings + r) * nm;
@@ -244,29 +257,95 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_synth(
     const bool even = (n % 2) == 0;
     const int h = n / 2;
     const int kmax = even ? h : n - 1;
-    // fold: F_k, k = 0..kmax
-    for (int k = threadIdx.x; k <= kmax; k += kRingThreads) {
-        double fr = 0.0, fi = 0.0;
-        for (int m = k; m <= mmax; m += n) {
-            const int i = minv[m];
-            if (i >= 0) {
-                const double2 D = phase_mode(drow[i], m, d.phi0, +1);
-                fr += D.x; fi += D.y;
+    const int tid = threadIdx.x;
+    // ---- fold the modes into F_k, k = 0..kmax (Sec. 2.2.2 wrap rule).
+    // Phases e^{i m phi0}: one sincos per thread for its first mode and one
+    // for the stride NT, then a complex multiply per further mode (a few ulp).
+    constexpr int kBatch = 8;
+    double2 step;   // e^{i NT phi0}
+    double2 ph;     // e^{i tid phi0}
+    {
+        double sn, cs;
+        sincos((double)NT * d.phi0, &sn, &cs);
+        step = make_double2(cs, sn);
+        sincos((double)tid * d.phi0, &sn, &cs);
+        ph = make_double2(cs, sn);
+    }
+    if (n > mmax) {
+        // each bin gets at most one direct mode m = k and one mirrored mode
+        // m = n - k: F_k = e^{i k phi0} (D_k + e^{-i n phi0} conj(D_{n-k}))
+        double2 cn;
+        {
+            double sn, cs;
+            sincos((double)n * d.phi0, &sn, &cs);
+            cn = make_double2(cs, -sn);
+        }
+        const int kdir = min(kmax, mmax);
+        for (int k0 = 0; k0 <= kmax; k0 += kBatch * NT) {
+            double2 raw[kBatch], rawc[kBatch];
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                const int k = k0 + q * NT + tid;
+                raw[q] = (k <= kdir) ? load_mode(drow, minv, mcontig, k) : make_double2(0.0, 0.0);
+                rawc[q] = (k >= 1 && k <= kmax && n - k <= mmax)
+                              ? load_mode(drow, minv, mcontig, n - k) : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                const int k = k0 + q * NT + tid;
+                if (k <= kmax) {
+                    double2 D = raw[q];
+                    if (k == 0) D.y = 0.0;
+                    D = cadd(D, cmul(cn, conjd(rawc[q])));
+                    buf[k] = cmul(ph, D);
+                }
+                ph = cmul(ph, step);
             }
         }
-        for (int m = n - k; m <= mmax; m += n) {
-            const int i = minv[m];
-            if (i >= 0) {
-                const double2 D = phase_mode(drow[i], m, d.phi0, +1);
-                fr += D.x; fi -= D.y;
+    } else {
+        // wrap-around: stage NT modes at a time in LDS; every bin adds the
+        // modes of the chunk congruent to +k and -k modulo n
+        for (int k = tid; k <= kmax; k += NT) buf[k] = make_double2(0.0, 0.0);
+        for (int base0 = 0; base0 <= mmax; base0 += kBatch * NT) {
+            double2 raw[kBatch];
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                const int m = base0 + q * NT + tid;
+                raw[q] = (m <= mmax) ? load_mode(drow, minv, mcontig, m) : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                const int base = base0 + q * NT;
+                if (base > mmax) break;
+                double2 D = raw[q];
+                if (base + tid == 0) D.y = 0.0;
+                Dc[tid] = cmul(ph, D);
+                ph = cmul(ph, step);
+                __syncthreads();
+                const int top = min(base + NT - 1, mmax);
+                for (int k = tid; k <= kmax; k += NT) {
+                    double2 F = buf[k];
+                    int mm = base + (((k - base) % n) + n) % n;      // first m >= base, m = k mod n
+                    for (; mm <= top; mm += n) {
+                        const double2 v = Dc[mm - base];
+                        F.x += v.x; F.y += v.y;
+                    }
+                    mm = base + ((((n - k) % n) - base) % n + n) % n;  // first m >= base, m = -k mod n
+                    if (mm == 0) mm = n;
+                    for (; mm <= top; mm += n) {
+                        const double2 v = Dc[mm - base];
+                        F.x += v.x; F.y -= v.y;
+                    }
+                    buf[k] = F;
+                }
+                __syncthreads();
             }
         }
-        buf[k] = make_double2(fr, fi);
     }
     __syncthreads();
     if (even) {
         const double2 *tw = pool + d.tw;
-        for (int k = threadIdx.x; k <= h / 2; k += kRingThreads) {
+        for (int k = tid; k <= h / 2; k += NT) {
             const int k2 = h - k;
             const double2 Fk = buf[k], Fk2 = buf[k2];
             const double2 e1 = cadd(Fk, conjd(Fk2)), o1 = csub(Fk, conjd(Fk2));
@@ -277,30 +356,33 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_synth(
             if (k2 != k) buf[k2] = Zk2;
         }
         __syncthreads();
-        ring_dft<kRingThreads>(buf, d, +1, pool);
+        ring_dft<NT, MAXN>(buf, d, +1, pool);
         if ((pix0 & 1) == 0) {
             double2 *o2 = reinterpret_cast<double2 *>(out);
-            for (int j = threadIdx.x; j < h; j += kRingThreads) o2[j] = buf[j];
+            for (int j = tid; j < h; j += NT) o2[j] = buf[j];
         } else {
-            for (int j = threadIdx.x; j < h; j += kRingThreads) {
+            for (int j = tid; j < h; j += NT) {
                 const double2 z = buf[j];
                 out[2 * j] = z.x;
                 out[2 * j + 1] = z.y;
             }
         }
     } else {
-        ring_dft<kRingThreads>(buf, d, +1, pool);
-        for (int j = threadIdx.x; j < n; j += kRingThreads) out[j] = buf[j].x;
+        ring_dft<NT, MAXN>(buf, d, +1, pool);
+        for (int j = tid; j < n; j += NT) out[j] = buf[j].x;
     }
 }
 
-__global__ __launch_bounds__(kRingThreads) void k_ring_anal(
-    const RingDesc *__restrict__ rings, const double2 *__restrict__ pool,
-    const double *__restrict__ map, long long npix, const int *__restrict__ mval, int nm,
-    int nrings, double2 *__restrict__ dt)
+// Analysis (adjoint of the synthesis): G_k by a real DFT, then
+// Dt_m = c_m e^{-i m phi0} G_{m mod n}.
+template <int NT, int MAXN>
+__global__ __launch_bounds__(NT, (MAXN <= 4096) ? 4 : 2) void k_ring_anal(
+    const int *__restrict__ ids, const RingDesc *__restrict__ rings,
+    const double2 *__restrict__ pool, const double *__restrict__ map, long long npix,
+    const int *__restrict__ mval, int mcontig, int nm, int nrings, double2 *__restrict__ dt)
 {
     extern __shared__ double2 buf[];
-    const int r = blockIdx.x;
+    const int r = ids[xcd_logical(blockIdx.x, gridDim.x)];
     const int b = blockIdx.y;
     const RingDesc d = rings[r];
     const long long pix0 = (long long)b * npix + d.start;
@@ -308,18 +390,18 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_anal(
     const int n = d.n;
     const bool even = (n % 2) == 0;
     const int h = n / 2;
+    const int tid = threadIdx.x;
     if (even) {
         if ((pix0 & 1) == 0) {
             const double2 *i2 = reinterpret_cast<const double2 *>(in);
-            for (int j = threadIdx.x; j < h; j += kRingThreads) buf[j] = i2[j];
+            for (int j = tid; j < h; j += NT) buf[j] = i2[j];
         } else {
-            for (int j = threadIdx.x; j < h; j += kRingThreads)
-                buf[j] = make_double2(in[2 * j], in[2 * j + 1]);
+            for (int j = tid; j < h; j += NT) buf[j] = make_double2(in[2 * j], in[2 * j + 1]);
         }
         __syncthreads();
-        ring_dft<kRingThreads>(buf, d, -1, pool);
+        ring_dft<NT, MAXN>(buf, d, -1, pool);
         const double2 *tw = pool + d.tw;
-        for (int k = threadIdx.x; k <= h / 2; k += kRingThreads) {
+        for (int k = tid; k <= h / 2; k += NT) {
             const int k2 = h - k;
             const double2 Zk = buf[k];
             const double2 Zk2 = buf[k2 == h ? 0 : k2];
@@ -333,23 +415,36 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_anal(
         }
         __syncthreads();
     } else {
-        for (int j = threadIdx.x; j < n; j += kRingThreads) buf[j] = make_double2(in[j], 0.0);
+        for (int j = tid; j < n; j += NT) buf[j] = make_double2(in[j], 0.0);
         __syncthreads();
-        ring_dft<kRingThreads>(buf, d, -1, pool);
+        ring_dft<NT, MAXN>(buf, d, -1, pool);
     }
     const int kmax = even ? h : n - 1;
     double2 *orow = dt + ((long long)b * nrings + r) * nm;
-    for (int i = threadIdx.x; i < nm; i += kRingThreads) {
+    double2 step, ph;   // e^{-i NT phi0}, e^{-i m phi0} for this thread's mode
+    {
+        double sn, cs;
+        sincos((double)NT * d.phi0, &sn, &cs);
+        step = make_double2(cs, -sn);
+    }
+    bool first = true;
+    for (int i = tid; i < nm; i += NT) {
         const int m = mval[i];
         const int kk = m % n;
         const double2 G = (kk <= kmax) ? buf[kk] : conjd(buf[n - kk]);
+        if (first || !mcontig) {
+            double sn, cs;
+            sincos((double)m * d.phi0, &sn, &cs);
+            ph = make_double2(cs, -sn);
+            first = false;
+        } else {
+            ph = cmul(ph, step);
+        }
         double2 v;
         if (m == 0) {
             v = make_double2(G.x, 0.0);
         } else {
-            double sn, cs;
-            sincos((double)m * d.phi0, &sn, &cs);
-            v = cmul(G, make_double2(cs, -sn));
+            v = cmul(G, ph);
             v.x *= 2.0; v.y *= 2.0;
         }
         orow[i] = v;
@@ -358,14 +453,14 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_anal(
 
 // Spectrum of the Bluestein kernel b_k = conj(c_k) (wrapped to negative k),
 // scaled by 1 / nb, one workgroup per listed ring.
-__global__ __launch_bounds__(kRingThreads) void k_bluestein_prep(
+__global__ __launch_bounds__(512) void k_bluestein_prep(
     const RingDesc *__restrict__ rings, const int *__restrict__ ids, double2 *pool)
 {
     extern __shared__ double2 buf[];
     const RingDesc d = rings[ids[blockIdx.x]];
     const int len = d.clen, nb = d.nb, two_len = 2 * len;
     const double2 *tch = pool + d.tch;
-    for (int k = threadIdx.x; k < nb; k += kRingThreads) {
+    for (int k = threadIdx.x; k < nb; k += 512) {
         int m = -1;
         if (k < len) m = k;
         else if (k > nb - len) m = nb - k;
@@ -374,9 +469,9 @@ __global__ __launch_bounds__(kRingThreads) void k_bluestein_prep(
         buf[k] = v;
     }
     __syncthreads();
-    fft_lds<kRingThreads>(buf, nb, -1, pool + d.twb, 1);
+    fft_lds<512, 8192>(buf, nb, -1, pool + d.twb, 1);
     const double inv = 1.0 / (double)nb;
-    for (int k = threadIdx.x; k < nb; k += kRingThreads)
+    for (int k = threadIdx.x; k < nb; k += 512)
         pool[d.bq + k] = make_double2(buf[k].x * inv, buf[k].y * inv);
 }
 
@@ -385,39 +480,63 @@ hipError_t set_lds(const void *fn, size_t bytes)
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+template <int NT, int MAXN>
+hipError_t synth_class(const sht_plan_s *p, int c, const double2 *delta, double *map,
+                       hipStream_t st)
+{
+    const RingClass &rc = p->cls[c];
+    if (rc.count == 0) return hipSuccess;
+    const size_t lds = (size_t)(rc.fft_entries + NT) * sizeof(double2);
+    hipError_t e = set_lds((const void *)k_ring_synth<NT, MAXN>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_ring_synth<NT, MAXN>), dim3((unsigned)rc.count, (unsigned)p->nmaps),
+                       dim3(NT), lds, st, rc.d_ids, p->d_rings, p->d_pool, delta, p->d_minv,
+                       p->mcontig, p->mmax, p->nm, p->nrings, map, p->npix, rc.fft_entries);
+    return hipGetLastError();
+}
+
+template <int NT, int MAXN>
+hipError_t anal_class(const sht_plan_s *p, int c, const double *map, double2 *dt, hipStream_t st)
+{
+    const RingClass &rc = p->cls[c];
+    if (rc.count == 0) return hipSuccess;
+    const size_t lds = (size_t)rc.fft_entries * sizeof(double2);
+    hipError_t e = set_lds((const void *)k_ring_anal<NT, MAXN>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_ring_anal<NT, MAXN>), dim3((unsigned)rc.count, (unsigned)p->nmaps),
+                       dim3(NT), lds, st, rc.d_ids, p->d_rings, p->d_pool, map, p->npix,
+                       p->d_mval, p->mcontig, p->nm, p->nrings, dt);
+    return hipGetLastError();
+}
+
 }  // namespace
 
+// Size classes (FFT length limit): 0 -> 2048, 1 -> 4096, 2 -> 8192.
 hipError_t launch_ring_synth(const sht_plan_s *p, const double2 *delta, double *map,
                              hipStream_t st)
 {
-    const size_t lds = (size_t)p->lds_complex * sizeof(double2);
-    hipError_t e = set_lds((const void *)k_ring_synth, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ring_synth, dim3((unsigned)p->nrings, (unsigned)p->nmaps),
-                       dim3(kRingThreads), lds, st, p->d_rings, p->d_pool, delta, p->d_minv,
-                       p->mmax, p->nm, p->nrings, map, p->npix);
-    return hipGetLastError();
+    hipError_t e = synth_class<512, 8192>(p, 2, delta, map, st);
+    if (e == hipSuccess) e = synth_class<512, 4096>(p, 1, delta, map, st);
+    if (e == hipSuccess) e = synth_class<256, 2048>(p, 0, delta, map, st);
+    return e;
 }
 
 hipError_t launch_ring_anal(const sht_plan_s *p, const double *map, double2 *dt, hipStream_t st)
 {
-    const size_t lds = (size_t)p->lds_complex * sizeof(double2);
-    hipError_t e = set_lds((const void *)k_ring_anal, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ring_anal, dim3((unsigned)p->nrings, (unsigned)p->nmaps),
-                       dim3(kRingThreads), lds, st, p->d_rings, p->d_pool, map, p->npix,
-                       p->d_mval, p->nm, p->nrings, dt);
-    return hipGetLastError();
+    hipError_t e = anal_class<512, 8192>(p, 2, map, dt, st);
+    if (e == hipSuccess) e = anal_class<512, 4096>(p, 1, map, dt, st);
+    if (e == hipSuccess) e = anal_class<256, 2048>(p, 0, map, dt, st);
+    return e;
 }
 
 hipError_t launch_bluestein_prep(const sht_plan_s *p, const int *ring_ids, int nids,
                                  hipStream_t st)
 {
     if (nids <= 0) return hipSuccess;
-    const size_t lds = (size_t)p->lds_complex * sizeof(double2);
+    const size_t lds = (size_t)8192 * sizeof(double2);
     hipError_t e = set_lds((const void *)k_bluestein_prep, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bluestein_prep, dim3((unsigned)nids), dim3(kRingThreads), lds, st,
+    hipLaunchKernelGGL(k_bluestein_prep, dim3((unsigned)nids), dim3(512), lds, st,
                        p->d_rings, ring_ids, p->d_pool);
     return hipGetLastError();
 }

@@ -43,6 +43,15 @@ struct PairDesc {
     int rs;       // ring index of the southern member, -1 if unpaired
 };
 
+// Rings grouped by FFT length for the Fourier kernels (LDS and register
+// budgets differ per class): class 0 up to 2048 points, 1 up to 4096, 2 up to 8192.
+struct RingClass {
+    int count;        // rings in the class
+    int fft_entries;  // LDS double2 entries of the spectrum / FFT buffer
+    int *d_ids;       // device [count] ring indices
+};
+constexpr int kNumRingClasses = 3;
+
 }  // namespace sht
 
 struct sht_plan_s {
@@ -65,8 +74,8 @@ struct sht_plan_s {
     double2 *d_pool;     // twiddle and Bluestein tables
     size_t table_bytes;
     size_t pool_entries;
-    int lds_complex;     // LDS double2 entries the Fourier kernels need
-    int ring_block;      // threads per workgroup of the Fourier kernels
+    int mcontig;         // m-set is 0..nm-1
+    sht::RingClass cls[sht::kNumRingClasses];
     size_t ws_ap_bytes;  // workspace: prescaled coefficients
     size_t ws_delta_bytes;
 };
@@ -80,6 +89,10 @@ hipError_t launch_legendre_fwd(const sht_plan_s *p, const double2 *ap, double2 *
 hipError_t launch_legendre_adj_ws(const sht_plan_s *p, const double2 *dt, double2 *part,
                                   double *alm, hipStream_t st);
 size_t adj_part_bytes(const sht_plan_s *p);
+size_t mfma_bf_bytes(const sht_plan_s *p);
+hipError_t launch_prescale_f32(const sht_plan_s *p, const double *alm, float *Bf, hipStream_t st);
+hipError_t launch_legendre_mfma_f32(const sht_plan_s *p, const float *Bf, double2 *delta,
+                                    hipStream_t st);
 hipError_t launch_ring_synth(const sht_plan_s *p, const double2 *delta, double *map,
                              hipStream_t st);
 hipError_t launch_ring_anal(const sht_plan_s *p, const double *map, double2 *dt, hipStream_t st);

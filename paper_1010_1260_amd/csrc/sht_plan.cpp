@@ -21,7 +21,6 @@ using sht::RingDesc;
 
 namespace {
 
-constexpr int kMaxLds = 8193;  // double2 entries of LDS a Fourier workgroup may use
 
 bool smooth7(long long n)
 {
@@ -31,11 +30,12 @@ bool smooth7(long long n)
     return n == 1;
 }
 
-int next_pow2(long long n)
+// smallest 7-smooth integer >= n
+int next_smooth7(long long n)
 {
-    int v = 1;
-    while (v < n) v <<= 1;
-    return v;
+    long long v = std::max(1LL, n);
+    while (!smooth7(v)) ++v;
+    return (int)v;
 }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -75,6 +75,10 @@ void free_tables(sht_plan_s *p)
                     p->d_minv, p->d_rings, p->d_pool};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    for (int c = 0; c < sht::kNumRingClasses; ++c) {
+        if (p->cls[c].d_ids) (void)hipFree(p->cls[c].d_ids);
+        p->cls[c].d_ids = nullptr;
+    }
     p->d_pairs = nullptr; p->d_mval = nullptr; p->d_moff = nullptr; p->d_mu = nullptr;
     p->d_A = nullptr; p->d_cn = nullptr; p->d_minv = nullptr; p->d_rings = nullptr;
     p->d_pool = nullptr;
@@ -162,6 +166,23 @@ struct PoolBuilder {
 
 }  // namespace
 
+// Prescale + Legendre stage of the forward transform into `delta`.
+static sht_status legendre_stage(sht_plan_t p, const double *alm, void *ws, double2 *delta,
+                                 hipStream_t st, hipEvent_t ev_mid)
+{
+    hipError_t e;
+    if (p->precision == SHT_FP32_MFMA) {
+        e = sht::launch_prescale_f32(p, alm, (float *)ws, st);
+        if (e == hipSuccess && ev_mid) e = hipEventRecord(ev_mid, st);
+        if (e == hipSuccess) e = sht::launch_legendre_mfma_f32(p, (const float *)ws, delta, st);
+    } else {
+        e = sht::launch_prescale(p, alm, (double2 *)ws, st);
+        if (e == hipSuccess && ev_mid) e = hipEventRecord(ev_mid, st);
+        if (e == hipSuccess) e = sht::launch_legendre_fwd(p, (const double2 *)ws, delta, st);
+    }
+    return e == hipSuccess ? SHT_OK : SHT_ERR_HIP;
+}
+
 extern "C" {
 
 const char *sht_version(void) { return "0.1.0"; }
@@ -191,7 +212,7 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     if (d->nrings < 1 || d->nmaps < 1) return SHT_ERR_INVALID_ARG;
     if (!d->cth || !d->sth || !d->phi0 || !d->nphi) return SHT_ERR_INVALID_ARG;
     if (d->flags & ~SHT_FLAG_NO_PAIRING) return SHT_ERR_INVALID_ARG;
-    if (d->precision != SHT_FP64) return SHT_ERR_UNSUPPORTED;
+    if (d->precision != SHT_FP64 && d->precision != SHT_FP32_MFMA) return SHT_ERR_UNSUPPORTED;
     std::vector<int32_t> mval(d->nm);
     for (int i = 0; i < d->nm; ++i) {
         mval[i] = d->mval ? d->mval[i] : i;
@@ -229,7 +250,8 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     }
     // ---- Fourier classification per ring
     std::vector<RingDesc> rings(R);
-    int lds = 1;
+    std::vector<int> ring_class(R);
+    int class_entries[sht::kNumRingClasses] = {0, 0, 0};
     for (int r = 0; r < R; ++r) {
         const long long n = d->nphi[r];
         RingDesc &g = rings[r];
@@ -239,18 +261,20 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
         g.n = (int)n;
         g.clen = (int)((n % 2 == 0) ? n / 2 : n);
         g.tw = g.tch = g.twb = g.bq = -1;
-        int need;
+        const int spec = (n % 2 == 0) ? g.clen + 1 : g.clen;  // F_k entries
+        int fftlen;
         if (smooth7(g.clen) && g.clen <= 8192) {
             g.nb = 0;
-            need = (n % 2 == 0) ? g.clen + 1 : g.clen;
-        } else if (2LL * g.clen - 1 <= 8192) {
-            g.nb = next_pow2(2LL * g.clen - 1);
-            need = std::max(g.nb, (n % 2 == 0) ? g.clen + 1 : g.clen);
+            fftlen = g.clen;
         } else {
-            return SHT_ERR_UNSUPPORTED;
+            g.nb = next_smooth7(2LL * g.clen - 1);
+            if (g.nb > 8192) return SHT_ERR_UNSUPPORTED;
+            fftlen = g.nb;
         }
-        if (need > kMaxLds) return SHT_ERR_UNSUPPORTED;
-        lds = std::max(lds, need);
+        const int need = std::max(spec, fftlen);
+        const int c = fftlen <= 2048 ? 0 : (fftlen <= 4096 ? 1 : 2);
+        ring_class[r] = c;
+        class_entries[c] = std::max(class_entries[c], need);
     }
 
     sht_plan_s *p = new (std::nothrow) sht_plan_s();
@@ -270,8 +294,9 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     p->moff[0] = 0;
     for (int i = 0; i < d->nm; ++i) p->moff[i + 1] = p->moff[i] + (d->lmax - mval[i] + 1);
     p->nalm = p->moff.back();
-    p->lds_complex = lds;
-    p->ring_block = 512;
+    p->mcontig = 1;
+    for (int i = 0; i < d->nm; ++i)
+        if (mval[i] != i) p->mcontig = 0;
 
     // ---- pairing of mirror rings (cos negated bitwise, sin equal)
     std::vector<PairDesc> pairs;
@@ -334,6 +359,20 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     if (st == SHT_OK) st = upload(&p->d_minv, minv, &tb);
     if (st == SHT_OK) st = upload(&p->d_rings, rings, &tb);
     if (st == SHT_OK) st = upload(&p->d_pool, pb.pool, &tb);
+    for (int c = 0; c < sht::kNumRingClasses && st == SHT_OK; ++c) {
+        // longest rings first (tail balance); rings of equal length adjacent so
+        // that consecutive workgroups, which the kernels place on one XCD,
+        // share twiddle and Bluestein tables in L2
+        std::vector<int> ids;
+        for (int r = 0; r < R; ++r)
+            if (ring_class[r] == c) ids.push_back(r);
+        std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
+            return d->nphi[a] > d->nphi[b];
+        });
+        p->cls[c].count = (int)ids.size();
+        p->cls[c].fft_entries = class_entries[c];
+        st = upload(&p->cls[c].d_ids, ids, &tb);
+    }
     if (st == SHT_OK && !prep_ids.empty()) {
         int *d_ids = nullptr;
         if (hipMalloc((void **)&d_ids, prep_ids.size() * sizeof(int)) != hipSuccess) {
@@ -353,7 +392,9 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
         return st;
     }
     p->table_bytes = tb;
-    p->ws_ap_bytes = align_up((size_t)p->nmaps * (size_t)p->nalm * sizeof(double2), 256);
+    p->ws_ap_bytes = align_up(p->precision == SHT_FP32_MFMA
+                                  ? sht::mfma_bf_bytes(p)
+                                  : (size_t)p->nmaps * (size_t)p->nalm * sizeof(double2), 256);
     p->ws_delta_bytes = align_up((size_t)p->nmaps * (size_t)R * (size_t)p->nm * sizeof(double2), 256);
     p->magic = sht::kPlanMagic;
     *out = p;
@@ -409,11 +450,7 @@ sht_status sht_alm2delta(sht_plan_t p, const double *alm, double *delta, void *w
     if (s != SHT_OK) return s;
     if (!alm || !delta) return SHT_ERR_INVALID_ARG;
     if (!ws || ws_bytes < p->ws_ap_bytes) return SHT_ERR_WORKSPACE;
-    hipStream_t st = (hipStream_t)stream;
-    double2 *ap = (double2 *)ws;
-    s = from_hip(sht::launch_prescale(p, alm, ap, st));
-    if (s != SHT_OK) return s;
-    return from_hip(sht::launch_legendre_fwd(p, ap, (double2 *)delta, st));
+    return legendre_stage(p, alm, ws, (double2 *)delta, (hipStream_t)stream, nullptr);
 }
 
 sht_status sht_delta2map(sht_plan_t p, const double *delta, double *map, void *stream)
@@ -432,10 +469,8 @@ sht_status sht_alm2map(sht_plan_t p, const double *alm, double *map, void *ws, s
     if (!alm || !map) return SHT_ERR_INVALID_ARG;
     if (!ws || ws_bytes < workspace_bytes(p)) return SHT_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
-    double2 *ap = (double2 *)ws;
     double2 *delta = (double2 *)((char *)ws + p->ws_ap_bytes);
-    s = from_hip(sht::launch_prescale(p, alm, ap, st));
-    if (s == SHT_OK) s = from_hip(sht::launch_legendre_fwd(p, ap, delta, st));
+    s = legendre_stage(p, alm, ws, delta, st, nullptr);
     if (s == SHT_OK) s = from_hip(sht::launch_ring_synth(p, delta, map, st));
     return s;
 }
@@ -450,12 +485,9 @@ sht_status sht_alm2map_events(sht_plan_t p, const double *alm, double *map, void
         if (!events[k]) return SHT_ERR_INVALID_ARG;
     if (!ws || ws_bytes < workspace_bytes(p)) return SHT_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
-    double2 *ap = (double2 *)ws;
     double2 *delta = (double2 *)((char *)ws + p->ws_ap_bytes);
     s = from_hip(hipEventRecord((hipEvent_t)events[0], st));
-    if (s == SHT_OK) s = from_hip(sht::launch_prescale(p, alm, ap, st));
-    if (s == SHT_OK) s = from_hip(hipEventRecord((hipEvent_t)events[1], st));
-    if (s == SHT_OK) s = from_hip(sht::launch_legendre_fwd(p, ap, delta, st));
+    if (s == SHT_OK) s = legendre_stage(p, alm, ws, delta, st, (hipEvent_t)events[1]);
     if (s == SHT_OK) s = from_hip(hipEventRecord((hipEvent_t)events[2], st));
     if (s == SHT_OK) s = from_hip(sht::launch_ring_synth(p, delta, map, st));
     if (s == SHT_OK) s = from_hip(hipEventRecord((hipEvent_t)events[3], st));

@@ -29,8 +29,10 @@ class Plan:
     ``device`` (default: the current CUDA/HIP device).
     """
 
+    PRECISIONS = {"fp64": 0, "fp32_mfma": 1}
+
     def __init__(self, lmax: int, geom, mval=None, nmaps: int = 1, pairing: bool = True,
-                 device=None):
+                 device=None, precision: str = "fp64"):
         lib = L.load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
@@ -56,7 +58,10 @@ class Plan:
         d.ringstart = (None if self._start is None
                        else self._start.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
         d.nmaps = self.nmaps
-        d.precision = L.SHT_FP64
+        if precision not in self.PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(self.PRECISIONS)}")
+        self.precision = precision
+        d.precision = self.PRECISIONS[precision]
         d.flags = 0 if pairing else L.SHT_FLAG_NO_PAIRING
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
