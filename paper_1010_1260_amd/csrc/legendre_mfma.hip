@@ -62,6 +62,42 @@ __device__ inline void swap_halves(float a, float b, float &lo, float &hi)
     hi = __uint_as_float(r[1]);
 }
 
+// One step of 4 l-values (j..j+3, all inside the m's range) for the four
+// 32x32 tiles: recurrence, FP32 conversion, half swap, four MFMAs.
+struct MfmaTiles {
+    v16f e0, e1, o0, o1;  // even / odd parity, rows 0-31 / 32-63
+};
+
+__device__ inline void mfma_step4(double x, double f, double &ua, double &ub, double A0,
+                                  double A1, double A2, double A3, float BE, float BO,
+                                  MfmaTiles &acc)
+{
+    const double u0 = fma(A0 * x, ub, -ua);
+    const double u1 = fma(A1 * x, u0, -ub);
+    const double u2 = fma(A2 * x, u1, -u0);
+    const double u3 = fma(A3 * x, u2, -u1);
+    ua = u2;
+    ub = u3;
+    float A0E, A1E, A0O, A1O;
+    swap_halves(tof(u0, f), tof(u2, f), A0E, A1E);
+    swap_halves(tof(u1, f), tof(u3, f), A0O, A1O);
+    acc.e0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0E, BE, acc.e0, 0, 0, 0);
+    acc.e1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1E, BE, acc.e1, 0, 0, 0);
+    acc.o0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0O, BO, acc.o0, 0, 0, 0);
+    acc.o1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1O, BO, acc.o1, 0, 0, 0);
+}
+
+__device__ inline void rescale_check(double &ua, double &ub, int &k, double &f)
+{
+    if (fmax(fabs(ua), fabs(ub)) > kTwoS) {
+        ua *= kTwoMinusS; ub *= kTwoMinusS;
+        k += 1;
+        f = final_scale(k);
+    }
+}
+
+constexpr int kBlk = 16;  // l-steps per unrolled block (4 MFMA steps)
+
 __device__ void mfma_one_m(double x, double s, int m, int i, long long off, double mum,
                            int lmax, const double *__restrict__ A, const float *__restrict__ Bg,
                            double *__restrict__ delta, const PairDesc *__restrict__ pairs,
@@ -72,7 +108,8 @@ __device__ void mfma_one_m(double x, double s, int m, int i, long long off, doub
     const int hi = lane >> 5;
     const int col = lane & 31;
     const double *__restrict__ Am = A + off;
-    const float *__restrict__ Bm = Bg + off * 32;
+    // lane's B element of row l: Bl[l * 32]; its K slot adds 2 rows in the upper half
+    const float *__restrict__ Bl = Bg + off * 32 + 2 * hi * 32 + col;
 
     double ua, ub;
     int k;
@@ -80,59 +117,128 @@ __device__ void mfma_one_m(double x, double s, int m, int i, long long off, doub
     double f = final_scale(k);
     ub = (len >= 2) ? (Am[1] * x) * ua : 0.0;
 
-    v16f acc0 = {}, acc1 = {}, acc2 = {}, acc3 = {};
-    v16f tot0 = {}, tot1 = {}, tot2 = {}, tot3 = {};
-    int it = 0;
-    for (int j = 0; j < len; j += 4, ++it) {
-        float X0, X1, X2, X3;
-        if (j == 0) {
-            X0 = tof(ua, f);
-            X1 = (len > 1) ? tof(ub, f) : 0.0f;
-            const double A2 = (2 < len) ? Am[2] : 0.0;
-            const double u2 = fma(A2 * x, ub, -ua);
-            const double A3 = (3 < len) ? Am[3] : 0.0;
-            const double u3 = fma(A3 * x, u2, -ub);
-            X2 = (2 < len) ? tof(u2, f) : 0.0f;
-            X3 = (3 < len) ? tof(u3, f) : 0.0f;
-            ua = u2; ub = u3;
-        } else {
-            const double A0 = Am[j];
-            const double A1 = (j + 1 < len) ? Am[j + 1] : 0.0;
-            const double A2 = (j + 2 < len) ? Am[j + 2] : 0.0;
-            const double A3 = (j + 3 < len) ? Am[j + 3] : 0.0;
-            const double u0 = fma(A0 * x, ub, -ua);
-            const double u1 = fma(A1 * x, u0, -ub);
-            const double u2 = fma(A2 * x, u1, -u0);
-            const double u3 = fma(A3 * x, u2, -u1);
-            X0 = tof(u0, f);
-            X1 = (j + 1 < len) ? tof(u1, f) : 0.0f;
-            X2 = (j + 2 < len) ? tof(u2, f) : 0.0f;
-            X3 = (j + 3 < len) ? tof(u3, f) : 0.0f;
-            ua = u2; ub = u3;
-        }
-        if (it & 1) {
-            if (fmax(fabs(ua), fabs(ub)) > kTwoS) {
-                ua *= kTwoMinusS; ub *= kTwoMinusS;
-                k += 1;
-                f = final_scale(k);
-            }
-        }
-        const int re = j + 2 * hi, ro = j + 1 + 2 * hi;
-        const float BE = (re < len) ? Bm[(long long)re * 32 + col] : 0.0f;
-        const float BO = (ro < len) ? Bm[(long long)ro * 32 + col] : 0.0f;
+    MfmaTiles acc, tot;
+    acc.e0 = v16f{}; acc.e1 = v16f{}; acc.o0 = v16f{}; acc.o1 = v16f{};
+    tot = acc;
+
+    // ---- j = 0..3 (seeds), guarded
+    {
+        const float X0 = tof(ua, f);
+        const float X1 = (len > 1) ? tof(ub, f) : 0.0f;
+        const double A2 = (2 < len) ? Am[2] : 0.0;
+        const double u2 = fma(A2 * x, ub, -ua);
+        const double A3 = (3 < len) ? Am[3] : 0.0;
+        const double u3 = fma(A3 * x, u2, -ub);
+        const float X2 = (2 < len) ? tof(u2, f) : 0.0f;
+        const float X3 = (3 < len) ? tof(u3, f) : 0.0f;
+        ua = u2; ub = u3;
+        const float BE = (2 * hi < len) ? Bl[0] : 0.0f;
+        const float BO = (1 + 2 * hi < len) ? Bl[32] : 0.0f;
         float A0E, A1E, A0O, A1O;
         swap_halves(X0, X2, A0E, A1E);
         swap_halves(X1, X3, A0O, A1O);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0E, BE, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1E, BE, acc1, 0, 0, 0);
-        acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0O, BO, acc2, 0, 0, 0);
-        acc3 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1O, BO, acc3, 0, 0, 0);
-        if ((it + 1) % kMfmaBlockIters == 0) {
-            tot0 += acc0; tot1 += acc1; tot2 += acc2; tot3 += acc3;
-            acc0 = v16f{}; acc1 = v16f{}; acc2 = v16f{}; acc3 = v16f{};
+        acc.e0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0E, BE, acc.e0, 0, 0, 0);
+        acc.e1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1E, BE, acc.e1, 0, 0, 0);
+        acc.o0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0O, BO, acc.o0, 0, 0, 0);
+        acc.o1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1O, BO, acc.o1, 0, 0, 0);
+    }
+
+    // ---- unrolled blocks of kBlk steps; the B operands of the next block are
+    // loaded while the current one computes (two register sets, alternating)
+    int j = 4;
+    int blk = 0;
+    if (j + kBlk <= len) {
+        float bx[8], by[8];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            bx[2 * t] = Bl[(long long)(j + 4 * t) * 32];
+            bx[2 * t + 1] = Bl[(long long)(j + 4 * t + 1) * 32];
+        }
+        while (true) {
+            // block on bx, prefetch into by
+            {
+                const int jn = j + kBlk;
+                const bool more = jn + kBlk <= len;
+                {
+                    // unconditional (clamped into the m's range) so that the
+                    // wait counts stay static; unused when !more
+                    const int jl = more ? jn : j;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        by[2 * t] = Bl[(long long)(jl + 4 * t) * 32];
+                        by[2 * t + 1] = Bl[(long long)(jl + 4 * t + 1) * 32];
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    mfma_step4(x, f, ua, ub, Am[j + 4 * t], Am[j + 4 * t + 1], Am[j + 4 * t + 2],
+                               Am[j + 4 * t + 3], bx[2 * t], bx[2 * t + 1], acc);
+                    if (t & 1) rescale_check(ua, ub, k, f);
+                }
+                if (++blk % (kMfmaBlockIters / 4) == 0) {
+                    tot.e0 += acc.e0; tot.e1 += acc.e1; tot.o0 += acc.o0; tot.o1 += acc.o1;
+                    acc.e0 = v16f{}; acc.e1 = v16f{}; acc.o0 = v16f{}; acc.o1 = v16f{};
+                }
+                j = jn;
+                if (!more) break;
+            }
+            // block on by, prefetch into bx
+            {
+                const int jn = j + kBlk;
+                const bool more = jn + kBlk <= len;
+                {
+                    // unconditional (clamped into the m's range) so that the
+                    // wait counts stay static; unused when !more
+                    const int jl = more ? jn : j;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        bx[2 * t] = Bl[(long long)(jl + 4 * t) * 32];
+                        bx[2 * t + 1] = Bl[(long long)(jl + 4 * t + 1) * 32];
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    mfma_step4(x, f, ua, ub, Am[j + 4 * t], Am[j + 4 * t + 1], Am[j + 4 * t + 2],
+                               Am[j + 4 * t + 3], by[2 * t], by[2 * t + 1], acc);
+                    if (t & 1) rescale_check(ua, ub, k, f);
+                }
+                if (++blk % (kMfmaBlockIters / 4) == 0) {
+                    tot.e0 += acc.e0; tot.e1 += acc.e1; tot.o0 += acc.o0; tot.o1 += acc.o1;
+                    acc.e0 = v16f{}; acc.e1 = v16f{}; acc.o0 = v16f{}; acc.o1 = v16f{};
+                }
+                j = jn;
+                if (!more) break;
+            }
         }
     }
-    tot0 += acc0; tot1 += acc1; tot2 += acc2; tot3 += acc3;
+
+    // ---- tail, guarded
+    for (; j < len; j += 4) {
+        const double A0 = Am[j];
+        const double A1 = (j + 1 < len) ? Am[j + 1] : 0.0;
+        const double A2 = (j + 2 < len) ? Am[j + 2] : 0.0;
+        const double A3 = (j + 3 < len) ? Am[j + 3] : 0.0;
+        const double u0 = fma(A0 * x, ub, -ua);
+        const double u1 = fma(A1 * x, u0, -ub);
+        const double u2 = fma(A2 * x, u1, -u0);
+        const double u3 = fma(A3 * x, u2, -u1);
+        const float X0 = tof(u0, f);
+        const float X1 = (j + 1 < len) ? tof(u1, f) : 0.0f;
+        const float X2 = (j + 2 < len) ? tof(u2, f) : 0.0f;
+        const float X3 = (j + 3 < len) ? tof(u3, f) : 0.0f;
+        ua = u2; ub = u3;
+        rescale_check(ua, ub, k, f);
+        const float BE = (j + 2 * hi < len) ? Bl[(long long)j * 32] : 0.0f;
+        const float BO = (j + 1 + 2 * hi < len) ? Bl[(long long)(j + 1) * 32] : 0.0f;
+        float A0E, A1E, A0O, A1O;
+        swap_halves(X0, X2, A0E, A1E);
+        swap_halves(X1, X3, A0O, A1O);
+        acc.e0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0E, BE, acc.e0, 0, 0, 0);
+        acc.e1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1E, BE, acc.e1, 0, 0, 0);
+        acc.o0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0O, BO, acc.o0, 0, 0, 0);
+        acc.o1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1O, BO, acc.o1, 0, 0, 0);
+    }
+    tot.e0 += acc.e0; tot.e1 += acc.e1; tot.o0 += acc.o0; tot.o1 += acc.o1;
 
     // D layout of the 32x32 tile: column = lane % 32, row = 8 (r/4) + 4 (lane/32) + r % 4
     const int map = grp * 16 + (col >> 1);
@@ -140,8 +246,8 @@ __device__ void mfma_one_m(double x, double s, int m, int i, long long off, doub
     const int part = col & 1;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const v16f &E = h ? tot1 : tot0;
-        const v16f &O = h ? tot3 : tot2;
+        const v16f &E = h ? tot.e1 : tot.e0;
+        const v16f &O = h ? tot.o1 : tot.o0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int row = 8 * (r >> 2) + 4 * hi + (r & 3);
