@@ -15,8 +15,8 @@
 // construction, then Dt_m = c_m e^{-i m phi0} G_{m mod n} (c_0 = 1, c_m = 2).
 //
 // One workgroup (512 threads) per ring and map; the whole ring lives in LDS.
-// DFTs of 7-smooth length run as a Stockham auto-sort FFT (radices 4, 2, 3,
-// 5, 7; every pass loads its butterfly inputs into registers, barriers, and
+// DFTs of 7-smooth length run as a Stockham auto-sort FFT (radices 8, 4, 2, 3,
+// 5, 7 and 8; every pass loads its butterfly inputs into registers, barriers, and
 // stores in place, so one LDS buffer suffices).  Other lengths use
 // Bluestein's chirp-z algorithm with a power-of-two convolution whose
 // kernel spectrum is precomputed at plan time.  Twiddles come from
@@ -76,6 +76,25 @@ __device__ inline void small_dft(double2 (&v)[R], int sign)
         v[2] = csub(s02, s13);
         v[1] = cadd(d02, d13);
         v[3] = csub(d02, d13);
+    } else if constexpr (R == 8) {
+        // two radix-4 DFTs of the even and odd inputs, combined with w8^k
+        double2 e[4] = {v[0], v[2], v[4], v[6]};
+        double2 o[4] = {v[1], v[3], v[5], v[7]};
+        small_dft<4>(e, sign);
+        small_dft<4>(o, sign);
+        constexpr double h = 0x1.6a09e667f3bcdp-1;  // 1/sqrt(2), correctly rounded
+        // w8 = e^{sign i pi/4}: w8^1 o1, w8^2 o2 = sign i o2, w8^3 o3
+        const double2 t1 = make_double2(h * (o[1].x - sign * o[1].y), h * (o[1].y + sign * o[1].x));
+        const double2 t2 = muli(o[2], sign);
+        const double2 t3 = make_double2(-h * (o[3].x + sign * o[3].y), h * (sign * o[3].x - o[3].y));
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], t1);
+        v[5] = csub(e[1], t1);
+        v[2] = cadd(e[2], t2);
+        v[6] = csub(e[2], t2);
+        v[3] = cadd(e[3], t3);
+        v[7] = csub(e[3], t3);
     } else {
         // odd R: pair r with R - r
         double2 sp[R / 2], dm[R / 2];
@@ -110,30 +129,37 @@ __device__ inline void small_dft(double2 (&v)[R], int sign)
 }
 
 // One Stockham pass of radix R over n <= MAXN points in LDS.  tw[idx * tws]
-// is e^{+2 pi i idx / n}.
+// is e^{+2 pi i idx / n}.  j / Ns is taken as umulhi(j, ceil(2^32 / Ns)),
+// which is exact for j, Ns < 2^13.
 template <int R, int NT, int MAXN>
 __device__ void fft_pass(double2 *buf, int n, int Ns, int sign, const double2 *__restrict__ tw,
                          int tws)
 {
     constexpr int MAXQ = (MAXN / R + NT - 1) / NT;
     const int nb = n / R;
-    const int tstep0 = n / (Ns * R);
+    const int tstep0 = (n / (Ns * R)) * tws;
+    const unsigned magic = (unsigned)((0x100000000ull + (unsigned)Ns - 1) / (unsigned)Ns);
     double2 v[MAXQ][R];
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
         const int j = threadIdx.x + q * NT;
         if (j < nb) {
-            const int k = j % Ns;
+            const int jq = (Ns == 1) ? j : (int)__umulhi((unsigned)j, magic);
+            const int k = j - jq * Ns;
             const int ts = tstep0 * k;
+            // twiddles w^r, r = 1..R-1, as powers of one table entry w = tw[ts]
+            double2 w1 = make_double2(1.0, 0.0);
+            if (ts != 0) {
+                w1 = tw[ts];
+                if (sign < 0) w1.y = -w1.y;
+            }
+            double2 wr = w1;
+            v[q][0] = buf[j];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                double2 x = buf[j + r * nb];
-                if (r > 0 && ts != 0) {
-                    double2 w = tw[(long long)(r * ts) * tws];
-                    if (sign < 0) w.y = -w.y;
-                    x = cmul(x, w);
-                }
-                v[q][r] = x;
+            for (int r = 1; r < R; ++r) {
+                const double2 x = buf[j + r * nb];
+                v[q][r] = (ts != 0) ? cmul(x, wr) : x;
+                wr = cmul(wr, w1);
             }
             small_dft<R>(v[q], sign);
         }
@@ -143,8 +169,9 @@ __device__ void fft_pass(double2 *buf, int n, int Ns, int sign, const double2 *_
     for (int q = 0; q < MAXQ; ++q) {
         const int j = threadIdx.x + q * NT;
         if (j < nb) {
-            const int k = j % Ns;
-            const int base = (j - k) * R + k;
+            const int jq = (Ns == 1) ? j : (int)__umulhi((unsigned)j, magic);
+            const int k = j - jq * Ns;
+            const int base = jq * Ns * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[q][r];
         }
@@ -159,7 +186,9 @@ __device__ void fft_lds(double2 *buf, int n, int sign, const double2 *__restrict
 {
     int Ns = 1, rem = n;
     while (rem > 1) {
-        if (rem % 4 == 0) {
+        if (rem % 8 == 0) {
+            fft_pass<8, NT, MAXN>(buf, n, Ns, sign, tw, tws); Ns *= 8; rem /= 8;
+        } else if (rem % 4 == 0) {
             fft_pass<4, NT, MAXN>(buf, n, Ns, sign, tw, tws); Ns *= 4; rem /= 4;
         } else if (rem % 2 == 0) {
             fft_pass<2, NT, MAXN>(buf, n, Ns, sign, tw, tws); Ns *= 2; rem /= 2;
@@ -176,20 +205,18 @@ __device__ void fft_lds(double2 *buf, int n, int sign, const double2 *__restrict
 // In-place DFT of any length len by Bluestein's algorithm:
 // e^{i 2 pi jk/len} = c_j c_k conj(c_{j-k}), c_k = e^{i pi k^2 / len}, as a
 // cyclic convolution of 7-smooth length nb >= 2 len - 1.
-// tch[q] = e^{2 pi i q / (2 len)}, twb = e^{2 pi i k / nb}, bq = DFT^-(conj c, wrapped) / nb.
+// chirp[k] = c_k (k < len), twb = e^{2 pi i k / nb}, bq = DFT^-(conj c, wrapped) / nb.
 // A sign -1 transform is conj(DFT^+(conj x)).
 template <int NT, int MAXN>
 __device__ void bluestein_lds(double2 *buf, int len, int nb, int sign,
-                              const double2 *__restrict__ tch, const double2 *__restrict__ twb,
+                              const double2 *__restrict__ chirp, const double2 *__restrict__ twb,
                               const double2 *__restrict__ bq)
 {
-    const int two_len = 2 * len;
     for (int k = threadIdx.x; k < nb; k += NT) {
         if (k < len) {
             double2 x = buf[k];
             if (sign < 0) x.y = -x.y;
-            const int q = (int)(((long long)k * k) % two_len);
-            buf[k] = cmul(x, tch[q]);
+            buf[k] = cmul(x, chirp[k]);
         } else {
             buf[k] = make_double2(0.0, 0.0);
         }
@@ -200,8 +227,7 @@ __device__ void bluestein_lds(double2 *buf, int len, int nb, int sign,
     __syncthreads();
     fft_lds<NT, MAXN>(buf, nb, +1, twb, 1);
     for (int j = threadIdx.x; j < len; j += NT) {
-        const int q = (int)(((long long)j * j) % two_len);
-        double2 z = cmul(buf[j], tch[q]);
+        double2 z = cmul(buf[j], chirp[j]);
         if (sign < 0) z.y = -z.y;
         buf[j] = z;
     }
@@ -239,7 +265,7 @@ __device__ inline double2 load_mode(const double2 *__restrict__ drow,
 // Synthesis: one workgroup per (ring of this size class, map).  LDS: the
 // spectrum / FFT buffer (fft_entries) followed by NT staging slots.
 template <int NT, int MAXN>
-__global__ __launch_bounds__(NT, (MAXN <= 4096) ? 4 : 2) void k_ring_synth(
+__global__ __launch_bounds__(NT, 4) void k_ring_synth(
     const int *__restrict__ ids, const RingDesc *__restrict__ rings,
     const double2 *__restrict__ pool, const double2 *__restrict__ delta,
     const int *__restrict__ minv, int mcontig, int mmax, int nm, int nrings,
@@ -303,42 +329,68 @@ __global__ __launch_bounds__(NT, (MAXN <= 4096) ? 4 : 2) void k_ring_synth(
             }
         }
     } else {
-        // wrap-around: stage NT modes at a time in LDS; every bin adds the
-        // modes of the chunk congruent to +k and -k modulo n
-        for (int k = tid; k <= kmax; k += NT) buf[k] = make_double2(0.0, 0.0);
-        for (int base0 = 0; base0 <= mmax; base0 += kBatch * NT) {
-            double2 raw[kBatch];
-#pragma unroll
-            for (int q = 0; q < kBatch; ++q) {
-                const int m = base0 + q * NT + tid;
-                raw[q] = (m <= mmax) ? load_mode(drow, minv, mcontig, m) : make_double2(0.0, 0.0);
-            }
-#pragma unroll
-            for (int q = 0; q < kBatch; ++q) {
-                const int base = base0 + q * NT;
-                if (base > mmax) break;
-                double2 D = raw[q];
-                if (base + tid == 0) D.y = 0.0;
-                Dc[tid] = cmul(ph, D);
-                ph = cmul(ph, step);
-                __syncthreads();
-                const int top = min(base + NT - 1, mmax);
-                for (int k = tid; k <= kmax; k += NT) {
-                    double2 F = buf[k];
-                    int mm = base + (((k - base) % n) + n) % n;      // first m >= base, m = k mod n
-                    for (; mm <= top; mm += n) {
-                        const double2 v = Dc[mm - base];
-                        F.x += v.x; F.y += v.y;
-                    }
-                    mm = base + ((((n - k) % n) - base) % n + n) % n;  // first m >= base, m = -k mod n
-                    if (mm == 0) mm = n;
-                    for (; mm <= top; mm += n) {
-                        const double2 v = Dc[mm - base];
-                        F.x += v.x; F.y -= v.y;
-                    }
-                    buf[k] = F;
+        // wrap-around (n <= mmax): bin k gathers its aliases m = k + j n and
+        // m = j n - k directly.  With w = e^{i n phi0},
+        //   F_k = e^{i k phi0} (sum_j Delta_{k+jn} w^j + sum_{j>=1} conj(Delta_{jn-k}) conj(w^j)).
+        // Few bins (small rings): G threads share a bin, each taking every
+        // G-th alias, and the G partial sums are added through LDS.
+        const int B = kmax + 1;
+        const int G = (B < NT) ? NT / B : 1;
+        const int kk = (G > 1) ? tid % B : tid;
+        const int g = (G > 1) ? tid / B : 0;
+        double2 stepG;   // w^G
+        {
+            double sn, cs;
+            sincos((double)n * (double)G * d.phi0, &sn, &cs);
+            stepG = make_double2(cs, sn);
+        }
+        double2 phb;     // e^{i k phi0} for this thread's first bin
+        {
+            double sn, cs;
+            sincos((double)kk * d.phi0, &sn, &cs);
+            phb = make_double2(cs, sn);
+        }
+        for (int k = kk; k <= kmax && g < G; k += NT) {
+            double sr = 0.0, si = 0.0;
+            int c = 0;
+            double2 wj = make_double2(1.0, 0.0);
+            for (int j = g; k + j * n <= mmax || (j >= 1 && j * n - k <= mmax); j += G, ++c) {
+                if ((c & 31) == 0) {   // re-seed w^j every 32 aliases
+                    double sn, cs;
+                    sincos((double)j * (double)n * d.phi0, &sn, &cs);
+                    wj = make_double2(cs, sn);
                 }
-                __syncthreads();
+                const int md = k + j * n;
+                if (md <= mmax) {
+                    double2 D = load_mode(drow, minv, mcontig, md);
+                    if (md == 0) D.y = 0.0;
+                    const double2 v = cmul(D, wj);
+                    sr += v.x; si += v.y;
+                }
+                const int mc = j * n - k;
+                if (j >= 1 && mc <= mmax) {
+                    const double2 D = load_mode(drow, minv, mcontig, mc);
+                    const double2 v = cmul(conjd(D), conjd(wj));
+                    sr += v.x; si += v.y;
+                }
+                wj = cmul(wj, stepG);
+            }
+            if (G > 1) {
+                Dc[g * B + k] = make_double2(sr, si);
+            } else {
+                buf[k] = cmul(phb, make_double2(sr, si));
+                phb = cmul(phb, step);
+            }
+        }
+        if (G > 1) {
+            __syncthreads();
+            if (tid < B) {
+                double sr = 0.0, si = 0.0;
+                for (int q = 0; q < G; ++q) {
+                    const double2 v = Dc[q * B + tid];
+                    sr += v.x; si += v.y;
+                }
+                buf[tid] = cmul(phb, make_double2(sr, si));
             }
         }
     }
@@ -376,7 +428,7 @@ __global__ __launch_bounds__(NT, (MAXN <= 4096) ? 4 : 2) void k_ring_synth(
 // Analysis (adjoint of the synthesis): G_k by a real DFT, then
 // Dt_m = c_m e^{-i m phi0} G_{m mod n}.
 template <int NT, int MAXN>
-__global__ __launch_bounds__(NT, (MAXN <= 4096) ? 4 : 2) void k_ring_anal(
+__global__ __launch_bounds__(NT, 4) void k_ring_anal(
     const int *__restrict__ ids, const RingDesc *__restrict__ rings,
     const double2 *__restrict__ pool, const double *__restrict__ map, long long npix,
     const int *__restrict__ mval, int mcontig, int nm, int nrings, double2 *__restrict__ dt)
@@ -458,15 +510,13 @@ __global__ __launch_bounds__(512) void k_bluestein_prep(
 {
     extern __shared__ double2 buf[];
     const RingDesc d = rings[ids[blockIdx.x]];
-    const int len = d.clen, nb = d.nb, two_len = 2 * len;
-    const double2 *tch = pool + d.tch;
+    const int len = d.clen, nb = d.nb;
+    const double2 *chirp = pool + d.tch;
     for (int k = threadIdx.x; k < nb; k += 512) {
         int m = -1;
         if (k < len) m = k;
         else if (k > nb - len) m = nb - k;
-        double2 v = make_double2(0.0, 0.0);
-        if (m >= 0) v = conjd(tch[(int)(((long long)m * m) % two_len)]);
-        buf[k] = v;
+        buf[k] = (m >= 0) ? conjd(chirp[m]) : make_double2(0.0, 0.0);
     }
     __syncthreads();
     fft_lds<512, 8192>(buf, nb, -1, pool + d.twb, 1);
@@ -515,7 +565,7 @@ hipError_t anal_class(const sht_plan_s *p, int c, const double *map, double2 *dt
 hipError_t launch_ring_synth(const sht_plan_s *p, const double2 *delta, double *map,
                              hipStream_t st)
 {
-    hipError_t e = synth_class<512, 8192>(p, 2, delta, map, st);
+    hipError_t e = synth_class<1024, 8192>(p, 2, delta, map, st);
     if (e == hipSuccess) e = synth_class<512, 4096>(p, 1, delta, map, st);
     if (e == hipSuccess) e = synth_class<256, 2048>(p, 0, delta, map, st);
     return e;
@@ -523,7 +573,7 @@ hipError_t launch_ring_synth(const sht_plan_s *p, const double2 *delta, double *
 
 hipError_t launch_ring_anal(const sht_plan_s *p, const double *map, double2 *dt, hipStream_t st)
 {
-    hipError_t e = anal_class<512, 8192>(p, 2, map, dt, st);
+    hipError_t e = anal_class<1024, 8192>(p, 2, map, dt, st);
     if (e == hipSuccess) e = anal_class<512, 4096>(p, 1, map, dt, st);
     if (e == hipSuccess) e = anal_class<256, 2048>(p, 0, map, dt, st);
     return e;

@@ -24,7 +24,7 @@ constexpr int kScaleStep = 512;
 struct RingDesc {
     long long start;  // first pixel of the ring in the map
     long long tw;     // offset (double2) of e^{+2 pi i k / n}, k < n
-    long long tch;    // offset of e^{+2 pi i q / (2 clen)}, q < 2 clen (Bluestein chirp)
+    long long tch;    // offset of the Bluestein chirp e^{i pi k^2 / clen}, k < clen
     long long twb;    // offset of e^{+2 pi i k / nb}, k < nb (Bluestein FFT)
     long long bq;     // offset of the Bluestein kernel spectrum (nb entries)
     double phi0;

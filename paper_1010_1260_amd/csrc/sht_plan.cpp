@@ -156,6 +156,23 @@ struct PoolBuilder {
         unit[len] = off;
         return off;
     }
+    // c_k = e^{i pi k^2 / len}, k < len, with the exact reduction k^2 mod 2 len
+    std::map<long long, long long> chirps;
+    long long chirp(long long len)
+    {
+        auto it = chirps.find(len);
+        if (it != chirps.end()) return it->second;
+        const long long off = (long long)pool.size();
+        pool.resize(pool.size() + len);
+        const long double pi = 3.141592653589793238462643383279502884L;
+        for (long long k = 0; k < len; ++k) {
+            const long long q = (k * k) % (2 * len);
+            const long double a = pi * (long double)q / (long double)len;
+            pool[off + k] = make_double2((double)std::cos(a), (double)std::sin(a));
+        }
+        chirps[len] = off;
+        return off;
+    }
     long long reserve(long long len)
     {
         const long long off = (long long)pool.size();
@@ -334,7 +351,7 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
         RingDesc &g = rings[r];
         g.tw = pb.roots(g.n);
         if (g.nb) {
-            g.tch = (g.n % 2 == 0) ? g.tw : pb.roots(2LL * g.clen);
+            g.tch = pb.chirp(g.clen);
             g.twb = pb.roots(g.nb);
             auto it = bq_of_len.find(g.clen);
             if (it == bq_of_len.end()) {
