@@ -174,6 +174,54 @@ sht_status sht_map2delta_adjoint(sht_plan_t plan, const double *map, double *del
 sht_status sht_delta2alm_adjoint(sht_plan_t plan, const double *delta, double *alm,
                                  void *ws, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Batches of maps with different l_max and geometry (not in the paper; for
+ * callers that transform many small and large maps together).  The batch
+ * refers to the device tables of single-map FP64 plans, which must outlive it.
+ * The Legendre stage of all maps runs as one persistent launch that takes
+ * (map, m-pair, ring-pair block) tiles, longest first, from an atomic
+ * counter; the counter only distributes work, so results are identical to
+ * the single-plan transforms and independent of the launch shape.  The
+ * per-ring Fourier step runs as one launch per ring size class.
+ * ------------------------------------------------------------------------- */
+typedef struct sht_batch_s *sht_batch_t;
+
+/* plans: host array of n plan handles, each with nmaps = 1 and SHT_FP64, all
+ * on the current device.  Uploads the work lists (device memory owned by
+ * the batch).  SHT_ERR_UNSUPPORTED for a batched or mixed-precision plan. */
+sht_status sht_plan_batch(sht_batch_t *out, const sht_plan_t *plans, int32_t n);
+sht_status sht_batch_destroy(sht_batch_t batch);
+sht_status sht_batch_workspace_size(sht_batch_t batch, size_t *bytes);
+
+/* alms: DEVICE array of n device pointers, alms[i] = complex128 [nalm_i] of
+ * map i; maps: DEVICE array of n device pointers, maps[i] = float64 [npix_i].
+ * ws: device workspace of sht_batch_workspace_size bytes.  Enqueues on
+ * `stream` only; no allocation, no synchronisation. */
+sht_status sht_alm2map_batch(sht_batch_t batch, const double *const *alms,
+                             double *const *maps, void *ws, size_t ws_bytes, void *stream);
+
+/* Launch shape of the batch: chains (ring pairs per lane: 1, 2 or 4) and
+ * persistent waves per compute unit (1..32). */
+sht_status sht_batch_get_config(sht_batch_t batch, int32_t *chains, int32_t *waves_per_cu);
+sht_status sht_batch_set_config(sht_batch_t batch, int32_t chains, int32_t waves_per_cu);
+
+/* Autotuner: times every (chains, waves per CU) candidate on the given
+ * buffers (synchronising `stream`) and keeps the fastest.  If cache_path is
+ * not NULL, a line "<batch signature> <chains> <waves_per_cu> <ms>" is looked
+ * up first (no timing if found) and appended after tuning.  The outputs are
+ * overwritten. */
+sht_status sht_batch_autotune(sht_batch_t batch, const double *const *alms,
+                              double *const *maps, void *ws, size_t ws_bytes,
+                              const char *cache_path, void *stream);
+
+/* Capture one sht_alm2map_batch on `stream` (not the null stream) into a HIP
+ * graph held by the batch; sht_batch_graph_launch replays it on any stream
+ * with the captured buffers.  Re-capturing replaces the graph. */
+sht_status sht_batch_graph_capture(sht_batch_t batch, const double *const *alms,
+                                   double *const *maps, void *ws, size_t ws_bytes,
+                                   void *stream);
+sht_status sht_batch_graph_launch(sht_batch_t batch, void *stream);
+
 /* Static description of a status code. */
 const char *sht_status_string(sht_status status);
 

@@ -9,7 +9,7 @@ from ._lib import ShtError, load
 
 load()
 
-from .sht import AlmToMap, Plan, alm2map  # noqa: E402
+from .sht import AlmToMap, Batch, Plan, alm2map  # noqa: E402
 
-__all__ = ["Plan", "AlmToMap", "alm2map", "ShtError", "load", "_lib"]
+__all__ = ["Plan", "Batch", "AlmToMap", "alm2map", "ShtError", "load", "_lib"]
 __version__ = "0.1.0"

@@ -31,6 +31,9 @@ EXPORTED = [
     "sht_plan", "sht_plan_destroy", "sht_plan_get_info", "sht_plan_workspace_size",
     "sht_alm2map", "sht_alm2map_events", "sht_alm2map_adjoint", "sht_alm2delta", "sht_delta2map",
     "sht_map2delta_adjoint", "sht_delta2alm_adjoint", "sht_status_string", "sht_version",
+    "sht_plan_batch", "sht_batch_destroy", "sht_batch_workspace_size", "sht_alm2map_batch",
+    "sht_batch_get_config", "sht_batch_set_config", "sht_batch_autotune",
+    "sht_batch_graph_capture", "sht_batch_graph_launch",
 ]
 
 
@@ -104,6 +107,20 @@ def load(path: str | None = None):
     for fn in ["sht_plan", "sht_plan_destroy", "sht_plan_get_info", "sht_plan_workspace_size",
                "sht_alm2map", "sht_alm2map_events", "sht_alm2map_adjoint", "sht_alm2delta", "sht_delta2map",
                "sht_map2delta_adjoint", "sht_delta2alm_adjoint"]:
+        getattr(L, fn).restype = ctypes.c_int
+    L.sht_plan_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int32]
+    L.sht_batch_destroy.argtypes = [vp]
+    L.sht_batch_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.sht_alm2map_batch.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.sht_batch_get_config.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]
+    L.sht_batch_set_config.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.sht_batch_autotune.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_char_p, vp]
+    L.sht_batch_graph_capture.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.sht_batch_graph_launch.argtypes = [vp, vp]
+    for fn in ["sht_plan_batch", "sht_batch_destroy", "sht_batch_workspace_size",
+               "sht_alm2map_batch", "sht_batch_get_config", "sht_batch_set_config",
+               "sht_batch_autotune", "sht_batch_graph_capture", "sht_batch_graph_launch"]:
         getattr(L, fn).restype = ctypes.c_int
     L.sht_status_string.argtypes = [ctypes.c_int]
     L.sht_status_string.restype = ctypes.c_char_p

@@ -332,6 +332,72 @@ __global__ void k_adj_reduce(const double2 *__restrict__ part, const double *__r
     *o = make_double2(sr * c, (e < m0len) ? 0.0 : si * c);
 }
 
+// ---------------------------------------------------------------- batches
+//
+// A batch of single-map FP64 plans of different l_max / geometry runs the
+// Legendre stage in one persistent launch: a fixed grid of waves takes
+// tiles (map, m-pair, ring-pair block) from a work list sorted longest
+// first, through an atomic counter.  The counter only hands out work; every
+// tile's arithmetic is the same as in the single-plan kernel, so results do
+// not depend on the schedule.  The counter is reset by a one-thread kernel
+// launched before the persistent kernel (no memset node, so the sequence can
+// be captured into a graph).
+
+__global__ void k_batch_reset(int *counter) { *counter = 0; }
+
+__global__ void k_batch_prescale(const BatchMap *__restrict__ maps,
+                                 const double *const *__restrict__ alms, char *__restrict__ ws)
+{
+    const BatchMap &bm = maps[blockIdx.y];
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= bm.nalm) return;
+    const double2 *a = reinterpret_cast<const double2 *>(alms[blockIdx.y]);
+    double2 v = a[e];
+    const double c = bm.cn[e];
+    v.x *= c;
+    v.y = (e < bm.m0len) ? 0.0 : v.y * c;
+    reinterpret_cast<double2 *>(ws + bm.ap_off)[e] = v;
+}
+
+template <int CH>
+__global__ __launch_bounds__(64) void k_legendre_fwd_batch(const BatchTile *__restrict__ tiles,
+                                                           int ntiles,
+                                                           const BatchMap *__restrict__ maps,
+                                                           char *__restrict__ ws,
+                                                           int *__restrict__ counter)
+{
+    const int lane = threadIdx.x;
+    for (;;) {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(counter, 1);
+        t = __shfl(t, 0);
+        if (t >= ntiles) break;
+        const BatchTile tile = tiles[t];
+        const BatchMap &bm = maps[tile.map];
+        Chains<CH> g;
+        double s[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int p = (tile.pblock * CH + c) * 64 + lane;
+            if (p < bm.npairs) {
+                const PairDesc d = bm.pairs[p];
+                g.x[c] = d.x; s[c] = d.s; g.rn[c] = d.rn; g.rs[c] = d.rs;
+            } else {
+                g.x[c] = 0.0; s[c] = 0.0; g.rn[c] = -1; g.rs[c] = -1;
+            }
+        }
+        const double2 *ap = reinterpret_cast<const double2 *>(ws + bm.ap_off);
+        double2 *delta = reinterpret_cast<double2 *>(ws + bm.delta_off);
+        const int q = tile.mpair;
+        for (int u = 0; u < 2; ++u) {
+            const int i = (u == 0) ? q : bm.nm - 1 - q;
+            if (u == 1 && i == q) break;
+            fwd_one_m<CH>(g, s, bm.mval[i], i, bm.moff[i], bm.mu[i], bm.lmax, bm.A, ap, delta, 0,
+                          bm.nm);
+        }
+    }
+}
+
 constexpr int kFwdChains = 2;
 constexpr int kAdjChains = 2;
 
@@ -383,6 +449,37 @@ hipError_t launch_legendre_adj_ws(const sht_plan_s *p, const double2 *dt, double
     dim3 grid((unsigned)((p->nalm + 255) / 256), (unsigned)p->nmaps);
     hipLaunchKernelGGL(k_adj_reduce, grid, dim3(256), 0, st, part, p->d_cn, alm, p->nalm,
                        pblocks, m0len);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_legendre(const BatchMap *maps, int nmaps, long long max_nalm,
+                                 const BatchTile *tiles, int ntiles, int chains, int grid_waves,
+                                 const double *const *alms, void *ws, int *counter,
+                                 hipStream_t st)
+{
+    dim3 pg((unsigned)((max_nalm + 255) / 256), (unsigned)nmaps);
+    hipLaunchKernelGGL(k_batch_prescale, pg, dim3(256), 0, st, maps, alms, (char *)ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, counter);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (chains) {
+    case 1:
+        hipLaunchKernelGGL(k_legendre_fwd_batch<1>, dim3((unsigned)grid_waves), dim3(64), 0, st,
+                           tiles, ntiles, maps, (char *)ws, counter);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_legendre_fwd_batch<2>, dim3((unsigned)grid_waves), dim3(64), 0, st,
+                           tiles, ntiles, maps, (char *)ws, counter);
+        break;
+    case 4:
+        hipLaunchKernelGGL(k_legendre_fwd_batch<4>, dim3((unsigned)grid_waves), dim3(64), 0, st,
+                           tiles, ntiles, maps, (char *)ws, counter);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

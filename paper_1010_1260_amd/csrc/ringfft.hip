@@ -264,21 +264,13 @@ __device__ inline double2 load_mode(const double2 *__restrict__ drow,
 
 // Synthesis: one workgroup per (ring of this size class, map).  LDS: the
 // spectrum / FFT buffer (fft_entries) followed by NT staging slots.
+// Synthesis of one ring: drow = its Delta_m row, out = its first pixel.
 template <int NT, int MAXN>
-__global__ __launch_bounds__(NT, 4) void k_ring_synth(
-    const int *__restrict__ ids, const RingDesc *__restrict__ rings,
-    const double2 *__restrict__ pool, const double2 *__restrict__ delta,
-    const int *__restrict__ minv, int mcontig, int mmax, int nm, int nrings,
-    double *__restrict__ map, long long npix, int dc_off)
+__device__ void synth_ring(double2 *buf, double2 *Dc, const RingDesc &d,
+                           const double2 *__restrict__ pool, const double2 *__restrict__ drow,
+                           const int *__restrict__ minv, int mcontig, int mmax,
+                           double *__restrict__ out)
 {
-    extern __shared__ double2 buf[];
-    double2 *Dc = buf + dc_off;
-    const int r = ids[xcd_logical(blockIdx.x, gridDim.x)];
-    const int b = blockIdx.y;
-    const RingDesc d = rings[r];
-    const double2 *drow = delta + ((long long)b * nrings + r) * nm;
-    const long long pix0 = (long long)b * npix + d.start;
-    double *out = map + pix0;
     const int n = d.n;
     const bool even = (n % 2) == 0;
     const int h = n / 2;
@@ -409,7 +401,7 @@ __global__ __launch_bounds__(NT, 4) void k_ring_synth(
         }
         __syncthreads();
         ring_dft<NT, MAXN>(buf, d, +1, pool);
-        if ((pix0 & 1) == 0) {
+        if ((reinterpret_cast<uintptr_t>(out) & 15) == 0) {
             double2 *o2 = reinterpret_cast<double2 *>(out);
             for (int j = tid; j < h; j += NT) o2[j] = buf[j];
         } else {
@@ -425,6 +417,36 @@ __global__ __launch_bounds__(NT, 4) void k_ring_synth(
     }
 }
 
+template <int NT, int MAXN>
+__global__ __launch_bounds__(NT, 4) void k_ring_synth(
+    const int *__restrict__ ids, const RingDesc *__restrict__ rings,
+    const double2 *__restrict__ pool, const double2 *__restrict__ delta,
+    const int *__restrict__ minv, int mcontig, int mmax, int nm, int nrings,
+    double *__restrict__ map, long long npix, int dc_off)
+{
+    extern __shared__ double2 buf[];
+    const int r = ids[xcd_logical(blockIdx.x, gridDim.x)];
+    const long long b = blockIdx.y;
+    const RingDesc d = rings[r];
+    synth_ring<NT, MAXN>(buf, buf + dc_off, d, pool, delta + (b * nrings + r) * nm, minv, mcontig,
+                         mmax, map + b * npix + d.start);
+}
+
+// Batched synthesis: work item (map, ring) of a batch of plans.
+template <int NT, int MAXN>
+__global__ __launch_bounds__(NT, 4) void k_ring_synth_batch(
+    const int2 *__restrict__ items, const BatchMap *__restrict__ maps,
+    double *const *__restrict__ outs, const char *__restrict__ ws, int dc_off)
+{
+    extern __shared__ double2 buf[];
+    const int2 it = items[xcd_logical(blockIdx.x, gridDim.x)];
+    const BatchMap &bm = maps[it.x];
+    const RingDesc d = bm.rings[it.y];
+    const double2 *delta = reinterpret_cast<const double2 *>(ws + bm.delta_off);
+    synth_ring<NT, MAXN>(buf, buf + dc_off, d, bm.pool, delta + (long long)it.y * bm.nm,
+                         bm.minv, bm.mcontig, bm.mmax, outs[it.x] + d.start);
+}
+
 // Analysis (adjoint of the synthesis): G_k by a real DFT, then
 // Dt_m = c_m e^{-i m phi0} G_{m mod n}.
 template <int NT, int MAXN>
@@ -437,14 +459,13 @@ __global__ __launch_bounds__(NT, 4) void k_ring_anal(
     const int r = ids[xcd_logical(blockIdx.x, gridDim.x)];
     const int b = blockIdx.y;
     const RingDesc d = rings[r];
-    const long long pix0 = (long long)b * npix + d.start;
-    const double *in = map + pix0;
+    const double *in = map + (long long)b * npix + d.start;
     const int n = d.n;
     const bool even = (n % 2) == 0;
     const int h = n / 2;
     const int tid = threadIdx.x;
     if (even) {
-        if ((pix0 & 1) == 0) {
+        if ((reinterpret_cast<uintptr_t>(in) & 15) == 0) {
             const double2 *i2 = reinterpret_cast<const double2 *>(in);
             for (int j = tid; j < h; j += NT) buf[j] = i2[j];
         } else {
@@ -576,6 +597,28 @@ hipError_t launch_ring_anal(const sht_plan_s *p, const double *map, double2 *dt,
     hipError_t e = anal_class<1024, 8192>(p, 2, map, dt, st);
     if (e == hipSuccess) e = anal_class<512, 4096>(p, 1, map, dt, st);
     if (e == hipSuccess) e = anal_class<256, 2048>(p, 0, map, dt, st);
+    return e;
+}
+
+template <int NT, int MAXN>
+hipError_t synth_batch_class(const BatchClass &bc, const BatchMap *maps, double *const *outs,
+                             const void *ws, hipStream_t st)
+{
+    if (bc.count == 0) return hipSuccess;
+    const size_t lds = (size_t)(bc.fft_entries + NT) * sizeof(double2);
+    hipError_t e = set_lds((const void *)k_ring_synth_batch<NT, MAXN>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_ring_synth_batch<NT, MAXN>), dim3((unsigned)bc.count), dim3(NT), lds, st,
+                       bc.d_items, maps, outs, (const char *)ws, bc.fft_entries);
+    return hipGetLastError();
+}
+
+hipError_t launch_ring_synth_batch(const BatchClass *cls, const BatchMap *maps,
+                                   double *const *outs, const void *ws, hipStream_t st)
+{
+    hipError_t e = synth_batch_class<1024, 8192>(cls[2], maps, outs, ws, st);
+    if (e == hipSuccess) e = synth_batch_class<512, 4096>(cls[1], maps, outs, ws, st);
+    if (e == hipSuccess) e = synth_batch_class<256, 2048>(cls[0], maps, outs, ws, st);
     return e;
 }
 

@@ -52,6 +52,35 @@ struct RingClass {
 };
 constexpr int kNumRingClasses = 3;
 
+// One map of a batch of plans (device side): the plan's tables plus the
+// offsets of the map's buffers inside the batch workspace.
+struct BatchMap {
+    const PairDesc *pairs;
+    const int32_t *mval;
+    const long long *moff;
+    const double *mu;
+    const double *A;
+    const double *cn;
+    const int32_t *minv;
+    const RingDesc *rings;
+    const double2 *pool;
+    long long nalm;
+    long long ap_off;     // prescaled coefficients (double2 [nalm]) in the workspace
+    long long delta_off;  // Delta (double2 [nrings][nm]) in the workspace
+    int lmax, mmax, nm, nrings, npairs, mcontig, m0len, pad;
+};
+
+// A tile of the persistent Legendre launch: map, m-pair, ring-pair block.
+struct BatchTile {
+    int map, mpair, pblock, pad;
+};
+
+struct BatchClass {
+    int count;        // (map, ring) items
+    int fft_entries;
+    int2 *d_items;    // device [count] (map, ring)
+};
+
 }  // namespace sht
 
 struct sht_plan_s {
@@ -75,6 +104,8 @@ struct sht_plan_s {
     size_t table_bytes;
     size_t pool_entries;
     int mcontig;         // m-set is 0..nm-1
+    std::vector<int> ring_class;  // size class of each ring's Fourier step
+    std::vector<int> ring_need;   // LDS double2 entries of each ring's spectrum / FFT
     sht::RingClass cls[sht::kNumRingClasses];
     size_t ws_ap_bytes;  // workspace: prescaled coefficients
     size_t ws_delta_bytes;
@@ -96,6 +127,12 @@ hipError_t launch_legendre_mfma_f32(const sht_plan_s *p, const float *Bf, double
 hipError_t launch_ring_synth(const sht_plan_s *p, const double2 *delta, double *map,
                              hipStream_t st);
 hipError_t launch_ring_anal(const sht_plan_s *p, const double *map, double2 *dt, hipStream_t st);
+hipError_t launch_batch_legendre(const BatchMap *maps, int nmaps, long long max_nalm,
+                                 const BatchTile *tiles, int ntiles, int chains, int grid_waves,
+                                 const double *const *alms, void *ws, int *counter,
+                                 hipStream_t st);
+hipError_t launch_ring_synth_batch(const BatchClass *cls, const BatchMap *maps,
+                                   double *const *outs, const void *ws, hipStream_t st);
 // Plan time: spectra of the Bluestein chirp kernels.
 hipError_t launch_bluestein_prep(const sht_plan_s *p, const int *ring_ids, int nids,
                                  hipStream_t st);

@@ -311,6 +311,13 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     p->moff[0] = 0;
     for (int i = 0; i < d->nm; ++i) p->moff[i + 1] = p->moff[i] + (d->lmax - mval[i] + 1);
     p->nalm = p->moff.back();
+    p->ring_class = ring_class;
+    p->ring_need.resize(R);
+    for (int r = 0; r < R; ++r) {
+        const RingDesc &g = rings[r];
+        const int spec = (g.n % 2 == 0) ? g.clen + 1 : g.clen;
+        p->ring_need[r] = std::max(spec, g.nb ? g.nb : g.clen);
+    }
     p->mcontig = 1;
     for (int i = 0; i < d->nm; ++i)
         if (mval[i] != i) p->mcontig = 0;

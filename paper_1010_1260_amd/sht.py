@@ -211,3 +211,104 @@ class AlmToMap(torch.autograd.Function):
 def alm2map(alm: torch.Tensor, plan: Plan) -> torch.Tensor:
     """Differentiable alm2map (autograd through AlmToMap)."""
     return AlmToMap.apply(alm, plan)
+
+
+class Batch:
+    """Maps of different l_max / geometry transformed together.
+
+    One persistent Legendre launch for all maps (work tiles sorted longest
+    first), one Fourier launch per ring size class; optional autotuning of the
+    launch shape and HIP graph capture.  The single-map FP64 plans must stay
+    alive as long as the batch (the batch keeps references to them).
+    """
+
+    def __init__(self, plans):
+        lib = L.load()
+        self.plans = list(plans)
+        self.device = self.plans[0].device
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(lib.sht_plan_batch(ctypes.byref(h), arr, len(self.plans)), "sht_plan_batch")
+        self._h = h
+        n = ctypes.c_size_t()
+        L.check(lib.sht_batch_workspace_size(h, ctypes.byref(n)), "sht_batch_workspace_size")
+        self.workspace_bytes = int(n.value)
+        self._ws = None
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.load().sht_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self) -> torch.Tensor:
+        if self._ws is None:
+            self._ws = torch.empty(max(1, self.workspace_bytes), dtype=torch.uint8,
+                                   device=self.device)
+        return self._ws
+
+    def new_maps(self):
+        return [p._new_map().reshape(-1) for p in self.plans]
+
+    def _ptrs(self, alms, outs):
+        if len(alms) != len(self.plans) or len(outs) != len(self.plans):
+            raise ValueError("one coefficient array and one map per plan")
+        for p, a, o in zip(self.plans, alms, outs):
+            if a.dtype != torch.complex128 or a.numel() != p.nalm or not a.is_contiguous():
+                raise ValueError("alm arrays must be contiguous complex128 of each plan's nalm")
+            if o.dtype != torch.float64 or o.numel() != p.npix or not o.is_contiguous():
+                raise ValueError("maps must be contiguous float64 of each plan's npix")
+        pa = torch.tensor([a.data_ptr() for a in alms], dtype=torch.int64, device=self.device)
+        po = torch.tensor([o.data_ptr() for o in outs], dtype=torch.int64, device=self.device)
+        return pa, po
+
+    def alm2map(self, alms, outs=None):
+        outs = self.new_maps() if outs is None else outs
+        pa, po = self._ptrs(alms, outs)
+        ws = self.workspace()
+        L.check(L.load().sht_alm2map_batch(self._h, _ptr(pa), _ptr(po), _ptr(ws), ws.numel(),
+                                           ctypes.c_void_p(_cur_stream(self.device))),
+                "sht_alm2map_batch")
+        return outs
+
+    @property
+    def config(self):
+        c = ctypes.c_int32()
+        w = ctypes.c_int32()
+        L.check(L.load().sht_batch_get_config(self._h, ctypes.byref(c), ctypes.byref(w)),
+                "sht_batch_get_config")
+        return int(c.value), int(w.value)
+
+    def set_config(self, chains: int, waves_per_cu: int):
+        L.check(L.load().sht_batch_set_config(self._h, chains, waves_per_cu),
+                "sht_batch_set_config")
+
+    def autotune(self, alms, outs, cache_path: str | None = None):
+        pa, po = self._ptrs(alms, outs)
+        ws = self.workspace()
+        cp = cache_path.encode() if cache_path else None
+        L.check(L.load().sht_batch_autotune(self._h, _ptr(pa), _ptr(po), _ptr(ws), ws.numel(),
+                                            cp, ctypes.c_void_p(_cur_stream(self.device))),
+                "sht_batch_autotune")
+        return self.config
+
+    def capture(self, alms, outs, stream: torch.cuda.Stream):
+        """Capture one batched transform into a HIP graph on `stream`."""
+        pa, po = self._ptrs(alms, outs)
+        ws = self.workspace()
+        self._keep = (pa, po, list(alms), list(outs))
+        L.check(L.load().sht_batch_graph_capture(self._h, _ptr(pa), _ptr(po), _ptr(ws),
+                                                 ws.numel(), ctypes.c_void_p(stream.cuda_stream)),
+                "sht_batch_graph_capture")
+
+    def replay(self, stream: torch.cuda.Stream | None = None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        L.check(L.load().sht_batch_graph_launch(self._h, ctypes.c_void_p(s.cuda_stream)),
+                "sht_batch_graph_launch")
