@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "maps/s at ℓmax=4096,nside=2048: mixed-precision vs FP64, rel err≤1e-6"
 PEAK_FP64 = 78.6e12    # MI355X FP64 vector FLOP/s
 PEAK_FP32_MFMA = 157.3e12
+PEAK_BF16_MFMA = 2.5e15   # dense
 PEAK_HBM = 8.0e12      # bytes/s
 
 
@@ -86,6 +87,56 @@ def run_plan(plan, alm, steps, warmup, lib, hip, torch, np):
     return wall, st.mean(axis=0), out
 
 
+def run_uneven(args, torch, np, W, dev):
+    """64 maps, l_max uniform over {256, 512, 1024, 2048}, nside = l_max / 2,
+    C_l = l^-2: one batch (persistent Legendre launch, autotuned, replayed
+    from a HIP graph) against the same maps one plan at a time."""
+    from paper_1010_1260_amd import Batch, Plan
+    lmaxes = W.uneven_lmax()
+    plans, alms = [], []
+    for i, L in enumerate(lmaxes):
+        plans.append(Plan(L, W.healpix_geometry(L // 2), device=dev))
+        alms.append(torch.from_numpy(W.random_alm(L, [4, i], spectrum="inv_l2")).to(dev))
+    b = Batch(plans)
+    outs = b.new_maps()
+    t0 = time.perf_counter()
+    cfg = b.autotune(alms, outs)
+    tune_s = time.perf_counter() - t0
+    s = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        b.capture(alms, outs, s)
+    for _ in range(args.warmup):
+        b.replay(s)
+    s.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(args.steps):
+        b.replay(s)
+    e1.record(s)
+    s.synchronize()
+    t_batch = e0.elapsed_time(e1) / args.steps
+    # same maps, one single-map transform after another
+    singles = [(p, a.reshape(1, -1)) for p, a in zip(plans, alms)]
+    for p, a in singles:
+        p.alm2map(a)
+    torch.cuda.synchronize()
+    e0.record()
+    for p, a in singles:
+        p.alm2map(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t_seq = e0.elapsed_time(e1)
+    # algorithmic Legendre flops of the batch: 8 per (ring pair, l, m)
+    flops = float(sum(p.npairs * p.nalm * 8 for p in plans))
+    return {"maps": len(plans), "lmax_counts": {str(L): lmaxes.count(L) for L in sorted(set(lmaxes))},
+            "ms_per_batch_graph": t_batch, "maps_per_s": len(plans) / (t_batch * 1e-3),
+            "ms_one_plan_at_a_time": t_seq, "speedup_vs_one_at_a_time": t_seq / t_batch,
+            "legendre_flops": flops, "overall_TFLOPs_legendre_work": flops / (t_batch * 1e-3) / 1e12,
+            "tuned_chains_waves_per_cu": list(cfg), "autotune_s": tune_s}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,8 +145,11 @@ def main() -> int:
     ap.add_argument("--lmax", type=int, default=4096)
     ap.add_argument("--nside", type=int, default=2048)
     ap.add_argument("--nmaps", type=int, default=16, help="batch of the mixed-precision run")
-    ap.add_argument("--only", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--only", choices=["all", "fp32_mfma", "bf16x3_mfma", "fp64"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--uneven", action="store_true",
+                    help="also time the batched uneven workload (64 maps, l_max in "
+                         "{256..2048}, one persistent launch, autotuned, graph replay)")
     ap.add_argument("--cpu-ring-stride", type=int, default=8,
                     help="oracle timed on every k-th ring (bounded CPU sample)")
     args = ap.parse_args()
@@ -122,18 +176,28 @@ def main() -> int:
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "data": "synthetic (seeded Gaussian a_lm, C_l = 1/(l(l+1)), HEALPix rings)"}
 
-    mixed = fp64 = None
-    if args.only in ("both", "mixed"):
-        plan = Plan(Lmax, geom, nmaps=B, precision="fp32_mfma", device=dev)
-        alm = torch.from_numpy(np.stack(alms_np)).to(dev)
-        wall, st, out = run_plan(plan, alm, args.steps, args.warmup, lib, hip, torch, np)
-        mixed = dict(plan=plan, wall=wall, st=st, out=out)
-        del alm
-    if args.only in ("both", "fp64"):
+    mixed_runs = {}
+    fp64 = None
+    for prec in ("fp32_mfma", "bf16x3_mfma"):
+        if args.only in ("all", prec):
+            plan = Plan(Lmax, geom, nmaps=B, precision=prec, device=dev)
+            alm = torch.from_numpy(np.stack(alms_np)).to(dev)
+            wall, st, out = run_plan(plan, alm, args.steps, args.warmup, lib, hip, torch, np)
+            mixed_runs[prec] = dict(plan=plan, wall=wall, st=st, out=out)
+            del alm
+            if args.only == "all":
+                # keep only the output of the run that may become the headline
+                pass
+    if args.only in ("all", "fp64"):
         plan64 = Plan(Lmax, geom, nmaps=1, device=dev)
         alm0 = torch.from_numpy(alms_np[0]).to(dev).reshape(1, -1)
         wall, st, out = run_plan(plan64, alm0, args.steps, args.warmup, lib, hip, torch, np)
         fp64 = dict(plan=plan64, wall=wall, st=st, out=out)
+    mixed = None
+    if mixed_runs:
+        best = max(mixed_runs, key=lambda k: 1.0 / mixed_runs[k]["wall"])
+        mixed = mixed_runs[best]
+        mixed["prec"] = best
 
     npairs = (mixed or fp64)["plan"].npairs
     nalm = (mixed or fp64)["plan"].nalm
@@ -155,49 +219,71 @@ def main() -> int:
         }
         res["fp64"] = fp64_info
     if mixed is not None:
+        forms = {}
+        for prec, run in mixed_runs.items():
+            t = run["wall"] / args.steps
+            leg = float(run["st"][1])
+            # algorithmic contraction flops: 4 per (ring pair, l, m, map) (complex
+            # accumulate of a real P_lm); the FP64 recurrence (4 per (pair, l, m))
+            # runs on the vector units beside it
+            flops = float(npairs) * float(nalm) * 4.0 * B
+            peak = PEAK_FP32_MFMA if prec == "fp32_mfma" else PEAK_BF16_MFMA
+            kern = "k_legendre_mfma_f32" if prec == "fp32_mfma" else "k_legendre_mfma_bf16x3"
+            executed = flops * (1 if prec == "fp32_mfma" else 6)
+            forms[prec] = {
+                "maps_per_s": B / t, "ms_per_step": t * 1e3,
+                "stages_ms": {"prescale": float(run["st"][0]), "legendre": leg,
+                              "ring_synthesis": float(run["st"][2])},
+                "roofline": {"bound": "mfma", "achieved": flops / (leg * 1e-3) / 1e12,
+                             "peak": peak / 1e12, "unit": "TFLOP/s",
+                             "frac": flops / (leg * 1e-3) / peak, "traffic": None,
+                             "kernel": kern, "flops_per_launch": flops,
+                             "executed_mfma_flops_per_launch": executed,
+                             "executed_frac": executed / (leg * 1e-3) / peak},
+            }
+        best = mixed["prec"]
         t = mixed["wall"] / args.steps
-        leg = float(mixed["st"][1])
-        # algorithmic contraction flops: 4 per (ring pair, l, m, map) (complex
-        # accumulate of a real P_lm); the FP64 recurrence (4 per (pair, l, m))
-        # runs on the vector units beside it
-        flops = float(npairs) * float(nalm) * 4.0 * B
+        fb = forms[best]
         res.update({
             "value": B / t, "unit": "maps/s", "ms_per_step": t * 1e3,
-            "dtype": "f32 matrix-core contraction + f64 recurrence and FFT",
+            "dtype": ("f32" if best == "fp32_mfma" else "bf16x3") +
+                     " matrix-core contraction + f64 recurrence and FFT",
             "config": {"workload": f"alm2map mixed precision, batch of {B} maps, lmax={Lmax}, "
                                    f"HEALPix nside={N}", "lmax": Lmax, "nside": N,
-                       "nmaps": B, "precision": "fp32_mfma", "npix": geom.npix,
+                       "nmaps": B, "precision": best, "npix": geom.npix,
                        "nrings": geom.nrings},
-            "stages_ms": {"prescale": float(mixed["st"][0]), "legendre": leg,
-                          "ring_synthesis": float(mixed["st"][2])},
-            "roofline": {"bound": "mfma", "achieved": flops / (leg * 1e-3) / 1e12,
-                         "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                         "frac": flops / (leg * 1e-3) / PEAK_FP32_MFMA, "traffic": None,
-                         "kernel": "k_legendre_mfma_f32", "flops_per_launch": flops},
+            "stages_ms": fb["stages_ms"],
+            "roofline": fb["roofline"],
+            "mixed_forms": forms,
             "fourier_stage": {"bytes_per_launch": fft_bytes_per_map * B,
                               "achieved_GBps": fft_bytes_per_map * B /
-                              (float(mixed["st"][2]) * 1e-3) / 1e9,
+                              (fb["stages_ms"]["ring_synthesis"] * 1e-3) / 1e9,
                               "frac_hbm": fft_bytes_per_map * B /
-                              (float(mixed["st"][2]) * 1e-3) / PEAK_HBM},
+                              (fb["stages_ms"]["ring_synthesis"] * 1e-3) / PEAK_HBM},
         })
         if fp64 is not None:
             res["speedup_mixed_vs_fp64"] = res["value"] / res["fp64"]["maps_per_s"]
-            # per-map error of every mixed map against the FP64 path on the GPU
-            errs = []
-            out_m = mixed["out"]
             p64 = fp64["plan"]
+            refs = []
             for i in range(B):
                 a = torch.from_numpy(alms_np[i]).to(dev).reshape(1, -1)
-                m64 = p64.alm2map(a)
-                errs.append(float(torch.linalg.norm(out_m[i] - m64[0]) / torch.linalg.norm(m64[0])))
-            res["rel_err_mixed_vs_fp64_gpu"] = {"max": max(errs), "mean": float(np.mean(errs)),
-                                                "maps": B}
+                refs.append(p64.alm2map(a)[0].clone())
+            for prec, run in mixed_runs.items():
+                errs = [float(torch.linalg.norm(run["out"][i] - refs[i]) / torch.linalg.norm(refs[i]))
+                        for i in range(B)]
+                forms[prec]["rel_err_vs_fp64_gpu"] = {"max": max(errs), "mean": float(np.mean(errs)),
+                                                      "maps": B}
+            res["rel_err_mixed_vs_fp64_gpu"] = forms[best]["rel_err_vs_fp64_gpu"]
+            del refs
     else:
         t = fp64["wall"] / args.steps
         res.update({"value": 1.0 / t, "unit": "maps/s", "ms_per_step": t * 1e3, "dtype": "f64",
                     "config": {"workload": f"alm2map FP64, 1 map, lmax={Lmax}, HEALPix nside={N}",
                                "lmax": Lmax, "nside": N, "nmaps": 1, "precision": "fp64"},
                     "roofline": dict(res["fp64"]["legendre_roofline"], traffic=None)})
+
+    if args.uneven:
+        res["uneven_batch"] = run_uneven(args, torch, np, W, dev)
 
     if not args.no_cpu_baseline:
         from oracle import ref
@@ -214,7 +300,7 @@ def main() -> int:
                                          f"{args.cpu_ring_stride}th), {tc:.1f} s wall, scaled "
                                          f"by ring count; CPU: {_cpu_model()}"}
         errs = {}
-        for name, runinfo in (("mixed", mixed), ("fp64", fp64)):
+        for name, runinfo in list(mixed_runs.items()) + [("fp64", fp64)]:
             if runinfo is None:
                 continue
             got = runinfo["out"][0].cpu().numpy()

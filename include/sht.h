@@ -67,11 +67,14 @@ typedef enum {
 
 typedef enum {
     SHT_FP64 = 0,      /* FP64 recurrence and FP64 accumulation                          */
-    SHT_FP32_MFMA = 1  /* FP64 recurrence; the l-sum of each batch of up to 16 maps runs on
+    SHT_FP32_MFMA = 1, /* FP64 recurrence; the l-sum of each batch of up to 16 maps runs on
                           the matrix cores with FP32 inputs (P_lm and prescaled a_lm
                           rounded to FP32) and two-level FP32 accumulation.  The ring
                           Fourier step and the adjoint stay FP64.  Relative L2 error of
                           a map against FP64 about 1e-7.                                  */
+    SHT_BF16X3_MFMA = 2 /* as SHT_FP32_MFMA, with every FP32 operand split into three BF16
+                           parts (8+8+8 bits) and six BF16 matrix-core products per
+                           tile; same accuracy class, higher matrix-core rate.          */
 } sht_precision;
 
 #define SHT_MAX_LMAX 16383

@@ -99,6 +99,7 @@ struct sht_plan_s {
     double *d_A;         // [nalm] normalised recurrence coefficient, see legendre.hip
     double *d_cn;        // [nalm] normalisation c_lm folded into the coefficients
     int32_t *d_minv;     // [mmax + 1] index of m in the set, -1 if absent
+    long long *d_boff;   // [nm] first 32-step block of each m (split-BF16 operand packing)
     sht::RingDesc *d_rings;
     double2 *d_pool;     // twiddle and Bluestein tables
     size_t table_bytes;
@@ -124,6 +125,11 @@ size_t mfma_bf_bytes(const sht_plan_s *p);
 hipError_t launch_prescale_f32(const sht_plan_s *p, const double *alm, float *Bf, hipStream_t st);
 hipError_t launch_legendre_mfma_f32(const sht_plan_s *p, const float *Bf, double2 *delta,
                                     hipStream_t st);
+size_t bf16_bytes(const sht_plan_s *p);
+hipError_t launch_prescale_bf16x3(const sht_plan_s *p, const double *alm, void *Bb,
+                                  hipStream_t st);
+hipError_t launch_legendre_mfma_bf16x3(const sht_plan_s *p, const void *Bb, double2 *delta,
+                                       hipStream_t st);
 hipError_t launch_ring_synth(const sht_plan_s *p, const double2 *delta, double *map,
                              hipStream_t st);
 hipError_t launch_ring_anal(const sht_plan_s *p, const double *map, double2 *dt, hipStream_t st);

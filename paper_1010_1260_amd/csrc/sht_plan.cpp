@@ -72,7 +72,7 @@ sht_status upload(T **dst, const std::vector<T> &src, size_t *acc)
 void free_tables(sht_plan_s *p)
 {
     void *ptrs[] = {p->d_pairs, p->d_mval, p->d_moff, p->d_mu, p->d_A, p->d_cn,
-                    p->d_minv, p->d_rings, p->d_pool};
+                    p->d_minv, p->d_rings, p->d_pool, p->d_boff};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (int c = 0; c < sht::kNumRingClasses; ++c) {
@@ -81,7 +81,7 @@ void free_tables(sht_plan_s *p)
     }
     p->d_pairs = nullptr; p->d_mval = nullptr; p->d_moff = nullptr; p->d_mu = nullptr;
     p->d_A = nullptr; p->d_cn = nullptr; p->d_minv = nullptr; p->d_rings = nullptr;
-    p->d_pool = nullptr;
+    p->d_pool = nullptr; p->d_boff = nullptr;
 }
 
 sht_status check_plan(sht_plan_t p)
@@ -192,6 +192,10 @@ static sht_status legendre_stage(sht_plan_t p, const double *alm, void *ws, doub
         e = sht::launch_prescale_f32(p, alm, (float *)ws, st);
         if (e == hipSuccess && ev_mid) e = hipEventRecord(ev_mid, st);
         if (e == hipSuccess) e = sht::launch_legendre_mfma_f32(p, (const float *)ws, delta, st);
+    } else if (p->precision == SHT_BF16X3_MFMA) {
+        e = sht::launch_prescale_bf16x3(p, alm, ws, st);
+        if (e == hipSuccess && ev_mid) e = hipEventRecord(ev_mid, st);
+        if (e == hipSuccess) e = sht::launch_legendre_mfma_bf16x3(p, ws, delta, st);
     } else {
         e = sht::launch_prescale(p, alm, (double2 *)ws, st);
         if (e == hipSuccess && ev_mid) e = hipEventRecord(ev_mid, st);
@@ -229,7 +233,9 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     if (d->nrings < 1 || d->nmaps < 1) return SHT_ERR_INVALID_ARG;
     if (!d->cth || !d->sth || !d->phi0 || !d->nphi) return SHT_ERR_INVALID_ARG;
     if (d->flags & ~SHT_FLAG_NO_PAIRING) return SHT_ERR_INVALID_ARG;
-    if (d->precision != SHT_FP64 && d->precision != SHT_FP32_MFMA) return SHT_ERR_UNSUPPORTED;
+    if (d->precision != SHT_FP64 && d->precision != SHT_FP32_MFMA &&
+        d->precision != SHT_BF16X3_MFMA)
+        return SHT_ERR_UNSUPPORTED;
     std::vector<int32_t> mval(d->nm);
     for (int i = 0; i < d->nm; ++i) {
         mval[i] = d->mval ? d->mval[i] : i;
@@ -381,6 +387,15 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     if (st == SHT_OK) st = upload(&p->d_A, A, &tb);
     if (st == SHT_OK) st = upload(&p->d_cn, cn, &tb);
     if (st == SHT_OK) st = upload(&p->d_minv, minv, &tb);
+    if (st == SHT_OK) {
+        std::vector<long long> boff(d->nm);
+        long long acc_b = 0;
+        for (int i = 0; i < d->nm; ++i) {
+            boff[i] = acc_b;
+            acc_b += (d->lmax - mval[i] + 1 + 31) / 32;
+        }
+        st = upload(&p->d_boff, boff, &tb);
+    }
     if (st == SHT_OK) st = upload(&p->d_rings, rings, &tb);
     if (st == SHT_OK) st = upload(&p->d_pool, pb.pool, &tb);
     for (int c = 0; c < sht::kNumRingClasses && st == SHT_OK; ++c) {
@@ -416,9 +431,11 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
         return st;
     }
     p->table_bytes = tb;
-    p->ws_ap_bytes = align_up(p->precision == SHT_FP32_MFMA
-                                  ? sht::mfma_bf_bytes(p)
-                                  : (size_t)p->nmaps * (size_t)p->nalm * sizeof(double2), 256);
+    p->ws_ap_bytes = align_up(
+        p->precision == SHT_FP32_MFMA     ? sht::mfma_bf_bytes(p)
+        : p->precision == SHT_BF16X3_MFMA ? sht::bf16_bytes(p)
+                                          : (size_t)p->nmaps * (size_t)p->nalm * sizeof(double2),
+        256);
     p->ws_delta_bytes = align_up((size_t)p->nmaps * (size_t)R * (size_t)p->nm * sizeof(double2), 256);
     p->magic = sht::kPlanMagic;
     *out = p;

@@ -29,7 +29,7 @@ class Plan:
     ``device`` (default: the current CUDA/HIP device).
     """
 
-    PRECISIONS = {"fp64": 0, "fp32_mfma": 1}
+    PRECISIONS = {"fp64": 0, "fp32_mfma": 1, "bf16x3_mfma": 2}
 
     def __init__(self, lmax: int, geom, mval=None, nmaps: int = 1, pairing: bool = True,
                  device=None, precision: str = "fp64"):

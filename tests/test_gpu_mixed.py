@@ -1,5 +1,5 @@
 """GPU parity of the mixed-precision batched Legendre stage (FP64 recurrence,
-FP32 matrix-core contraction) against the FP64 oracle.  Bound: relative L2
+FP32 or 3-way split BF16 matrix-core contraction) against the FP64 oracle.  Bound: relative L2
 error <= 1e-6 per map (the target for the mixed forms); the emulated error of
 the two-level FP32 accumulation is about 1e-7."""
 import sys
@@ -37,13 +37,18 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+PRECS = ["fp32_mfma", "bf16x3_mfma"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("lmax,nside,nmaps", [(64, 32, 1), (200, 64, 3), (255, 100, 16),
-                                              (130, 40, 17)])
-def test_mixed_delta_and_map_parity(P, lmax, nside, nmaps):
-    _say("mixed fp32 delta/map", lmax, nside, nmaps)
+                                              (130, 40, 17), (31, 16, 2), (0, 2, 1), (1, 2, 2)])
+def test_mixed_delta_and_map_parity(P, lmax, nside, nmaps, prec):
+    _say("mixed delta/map", prec, lmax, nside, nmaps)
     g = W.healpix_geometry(nside)
-    alms = np.stack([W.random_alm(lmax, [301, lmax, i]) for i in range(nmaps)])
-    plan = P.Plan(lmax, g, nmaps=nmaps, precision="fp32_mfma")
+    alms = np.stack([W.random_alm(lmax, [301, lmax, i], spectrum="flat" if lmax < 2 else "inv_l_lp1")
+                     for i in range(nmaps)])
+    plan = P.Plan(lmax, g, nmaps=nmaps, precision=prec)
     a = torch.from_numpy(alms).to(_dev())
     d = plan.alm2delta(a).cpu().numpy()
     mp = plan.alm2map(a).cpu().numpy()
@@ -54,38 +59,41 @@ def test_mixed_delta_and_map_parity(P, lmax, nside, nmaps):
         assert _rel(mp[i], em) < TOL, i
 
 
-def test_mixed_partial_mset_ragged(P):
-    _say("mixed fp32 partial m-set, ragged")
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixed_partial_mset_ragged(P, prec):
+    _say("mixed partial m-set, ragged", prec)
     lmax = 97
     mval = np.array([0, 1, 5, 6, 7, 40, 41, 90, 97], np.int32)
     g = W.ecp_geometry(37, 21)
     alms = np.stack([W.random_alm(lmax, [302, i], mval=mval) for i in range(5)])
-    plan = P.Plan(lmax, g, mval=mval, nmaps=5, precision="fp32_mfma")
+    plan = P.Plan(lmax, g, mval=mval, nmaps=5, precision=prec)
     d = plan.alm2delta(torch.from_numpy(alms).to(_dev())).cpu().numpy()
     for i in range(5):
         e = ref.delta(lmax, mval, g.cth, g.sth, alms[i])
         assert _rel(d[i], e) < TOL
 
 
-def test_mixed_matches_fp64_path(P):
-    _say("mixed vs fp64 kernel")
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixed_matches_fp64_path(P, prec):
+    _say("mixed vs fp64 kernel", prec)
     lmax, nside, nmaps = 300, 128, 4
     g = W.healpix_geometry(nside)
     alms = np.stack([W.random_alm(lmax, [303, i]) for i in range(nmaps)])
     a = torch.from_numpy(alms).to(_dev())
     m64 = P.Plan(lmax, g, nmaps=nmaps).alm2map(a).cpu().numpy()
-    m32 = P.Plan(lmax, g, nmaps=nmaps, precision="fp32_mfma").alm2map(a).cpu().numpy()
+    m32 = P.Plan(lmax, g, nmaps=nmaps, precision=prec).alm2map(a).cpu().numpy()
     for i in range(nmaps):
         assert _rel(m32[i], m64[i]) < TOL
 
 
 @pytest.mark.slow
-def test_mixed_l4096_nside2048_x16_sampled(P):
-    _say("mixed l4096 nside2048 x16 sampled rings")
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixed_l4096_nside2048_x16_sampled(P, prec):
+    _say("mixed l4096 nside2048 x16 sampled rings", prec)
     L, N, nmaps = 4096, 2048, 16
     g = W.healpix_geometry(N)
     alms = [W.random_alm(L, [3, i]) for i in range(nmaps)]
-    plan = P.Plan(L, g, nmaps=nmaps, precision="fp32_mfma")
+    plan = P.Plan(L, g, nmaps=nmaps, precision=prec)
     out = plan.alm2map(torch.from_numpy(np.stack(alms)).to(_dev()))
     torch.cuda.synchronize()
     out = out.cpu().numpy()
