@@ -51,6 +51,20 @@ def _cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def recorded_traffic(key):
+    """HBM bytes per launch recorded from rocprofv3 counters (profiles/traffic.json),
+    or None when absent or when the kernel source changed since."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[key]
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
+            return None
+        return float(rec["bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def run_plan(plan, alm, steps, warmup, lib, hip, torch, np):
     """Time `steps` transforms after `warmup`; returns wall seconds, stage ms, output."""
     dev = plan.device
@@ -150,6 +164,9 @@ def main() -> int:
     ap.add_argument("--uneven", action="store_true",
                     help="also time the batched uneven workload (64 maps, l_max in "
                          "{256..2048}, one persistent launch, autotuned, graph replay)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before timing, copy this many MiB device to device (a copy of known "
+                         "size for scaling hardware byte counters)")
     ap.add_argument("--cpu-ring-stride", type=int, default=8,
                     help="oracle timed on every k-th ring (bounded CPU sample)")
     args = ap.parse_args()
@@ -169,6 +186,13 @@ def main() -> int:
     hip = _hip()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     Lmax, N, B = args.lmax, args.nside, args.nmaps
     geom = W.healpix_geometry(N)
     alms_np = [W.random_alm(Lmax, [3, i]) for i in range(B)]
@@ -230,13 +254,14 @@ def main() -> int:
             peak = PEAK_FP32_MFMA if prec == "fp32_mfma" else PEAK_BF16_MFMA
             kern = "k_legendre_mfma_f32" if prec == "fp32_mfma" else "k_legendre_mfma_bf16x3"
             executed = flops * (1 if prec == "fp32_mfma" else 6)
+            traffic = recorded_traffic(f"{kern}|lmax={Lmax}|nside={N}|nmaps={B}")
             forms[prec] = {
                 "maps_per_s": B / t, "ms_per_step": t * 1e3,
                 "stages_ms": {"prescale": float(run["st"][0]), "legendre": leg,
                               "ring_synthesis": float(run["st"][2])},
                 "roofline": {"bound": "mfma", "achieved": flops / (leg * 1e-3) / 1e12,
                              "peak": peak / 1e12, "unit": "TFLOP/s",
-                             "frac": flops / (leg * 1e-3) / peak, "traffic": None,
+                             "frac": flops / (leg * 1e-3) / peak, "traffic": traffic,
                              "kernel": kern, "flops_per_launch": flops,
                              "executed_mfma_flops_per_launch": executed,
                              "executed_frac": executed / (leg * 1e-3) / peak},

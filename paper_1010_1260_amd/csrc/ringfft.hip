@@ -132,7 +132,7 @@ __device__ inline void small_dft(double2 (&v)[R], int sign)
 // is e^{+2 pi i idx / n}.  j / Ns is taken as umulhi(j, ceil(2^32 / Ns)),
 // which is exact for j, Ns < 2^13.
 template <int R, int NT, int MAXN>
-__device__ void fft_pass(double2 *buf, int n, int Ns, int sign, const double2 *__restrict__ tw,
+__device__ __attribute__((always_inline)) inline void fft_pass(double2 *buf, int n, int Ns, int sign, const double2 *__restrict__ tw,
                          int tws)
 {
     constexpr int MAXQ = (MAXN / R + NT - 1) / NT;
@@ -182,7 +182,7 @@ __device__ void fft_pass(double2 *buf, int n, int Ns, int sign, const double2 *_
 // In-place DFT of 7-smooth length n <= MAXN:
 // buf_k <- sum_j buf_j e^{sign 2 pi i j k / n}.
 template <int NT, int MAXN>
-__device__ void fft_lds(double2 *buf, int n, int sign, const double2 *__restrict__ tw, int tws)
+__device__ __attribute__((always_inline)) inline void fft_lds(double2 *buf, int n, int sign, const double2 *__restrict__ tw, int tws)
 {
     int Ns = 1, rem = n;
     while (rem > 1) {
@@ -208,7 +208,7 @@ __device__ void fft_lds(double2 *buf, int n, int sign, const double2 *__restrict
 // chirp[k] = c_k (k < len), twb = e^{2 pi i k / nb}, bq = DFT^-(conj c, wrapped) / nb.
 // A sign -1 transform is conj(DFT^+(conj x)).
 template <int NT, int MAXN>
-__device__ void bluestein_lds(double2 *buf, int len, int nb, int sign,
+__device__ __attribute__((always_inline)) inline void bluestein_lds(double2 *buf, int len, int nb, int sign,
                               const double2 *__restrict__ chirp, const double2 *__restrict__ twb,
                               const double2 *__restrict__ bq)
 {
@@ -266,7 +266,7 @@ __device__ inline double2 load_mode(const double2 *__restrict__ drow,
 // spectrum / FFT buffer (fft_entries) followed by NT staging slots.
 // Synthesis of one ring: drow = its Delta_m row, out = its first pixel.
 template <int NT, int MAXN>
-__device__ void synth_ring(double2 *buf, double2 *Dc, const RingDesc &d,
+__device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, double2 *Dc, const RingDesc &d,
                            const double2 *__restrict__ pool, const double2 *__restrict__ drow,
                            const int *__restrict__ minv, int mcontig, int mmax,
                            double *__restrict__ out)
