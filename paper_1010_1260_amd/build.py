@@ -20,6 +20,10 @@ HIPCC_FLAGS = [
     "-shared",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in ordinary VGPRs: the block sums are added
+    # with plain VALU adds (no AGPR copies) and zero-started blocks take an
+    # inline 0 accumulator
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -31,7 +31,6 @@ namespace {
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 
-constexpr int kMfmaBlockIters = 32;  // iterations (4 l-steps each) per FP32 block: 64 terms per parity
 
 __global__ void k_prescale_f32(const double2 *__restrict__ alm, const double *__restrict__ cn,
                                float *__restrict__ Bf, long long nalm, int nmaps, long long m0len)
@@ -52,7 +51,30 @@ __global__ void k_prescale_f32(const double2 *__restrict__ alm, const double *__
     Bf[((long long)grp * nalm + e) * 32 + col] = v;
 }
 
-__device__ inline float tof(double u, double f) { return (float)(u * f); }
+// Lane state of the mixed kernels.  u = P_l / c_l is carried as v 2^(512 k),
+// k <= 0, as in the FP64 kernel, but a lane moves up to k = 0 as soon as its
+// true value passes 2^-400 (|v| > 2^112 at k = -1).  Checked every 16 steps
+// (growth below 2^140), every lane with k < 0 then holds a true value below
+// 2^-260, which is zero in FP32: the matrix operand is (float)v for k = 0 and
+// 0 otherwise.  Values at k = 0 are bounded by sqrt((2l+1)/4pi)/c_l < 2^9
+// (addition theorem), so a wave whose lanes all reached k = 0 -- almost every
+// wave past its first l-steps -- needs neither the mask nor any rescaling.
+constexpr double kEmerge = 0x1p112;
+
+__device__ inline void rescale_mixed(double &ua, double &ub, int &k)
+{
+    if (k < 0) {
+        const double lim = (k == -1) ? kEmerge : kTwoS;
+        if (fmax(fabs(ua), fabs(ub)) > lim) {
+            ua *= kTwoMinusS; ub *= kTwoMinusS;
+            k += 1;
+        }
+    }
+}
+
+__device__ inline bool wave_any(bool c) { return __builtin_amdgcn_ballot_w64(c) != 0; }
+
+__device__ inline float opnd(double u, bool live) { return live ? (float)u : 0.0f; }
 
 __device__ inline void swap_halves(float a, float b, float &lo, float &hi)
 {
@@ -62,41 +84,88 @@ __device__ inline void swap_halves(float a, float b, float &lo, float &hi)
     hi = __uint_as_float(r[1]);
 }
 
-// One step of 4 l-values (j..j+3, all inside the m's range) for the four
-// 32x32 tiles: recurrence, FP32 conversion, half swap, four MFMAs.
 struct MfmaTiles {
     v16f e0, e1, o0, o1;  // even / odd parity, rows 0-31 / 32-63
 };
 
-__device__ inline void mfma_step4(double x, double f, double &ua, double &ub, double A0,
-                                  double A1, double A2, double A3, float BE, float BO,
-                                  MfmaTiles &acc)
+// Four MFMAs of one group of 4 l-values: X0..X3 = P_l..P_{l+3} of the lane's
+// ring pair; BE / BO = the lane's B elements of the even / odd rows.
+__device__ __forceinline__ void mfma4(float X0, float X1, float X2, float X3, float BE, float BO,
+                                      MfmaTiles &acc)
 {
-    const double u0 = fma(A0 * x, ub, -ua);
-    const double u1 = fma(A1 * x, u0, -ub);
-    const double u2 = fma(A2 * x, u1, -u0);
-    const double u3 = fma(A3 * x, u2, -u1);
-    ua = u2;
-    ub = u3;
     float A0E, A1E, A0O, A1O;
-    swap_halves(tof(u0, f), tof(u2, f), A0E, A1E);
-    swap_halves(tof(u1, f), tof(u3, f), A0O, A1O);
+    swap_halves(X0, X2, A0E, A1E);
+    swap_halves(X1, X3, A0O, A1O);
     acc.e0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0E, BE, acc.e0, 0, 0, 0);
     acc.e1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1E, BE, acc.e1, 0, 0, 0);
     acc.o0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0O, BO, acc.o0, 0, 0, 0);
     acc.o1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1O, BO, acc.o1, 0, 0, 0);
 }
 
-__device__ inline void rescale_check(double &ua, double &ub, int &k, double &f)
+constexpr int kBlk = 16;    // l-steps per block (4 groups of 4)
+constexpr int kSuper = 8;   // blocks per flush of the first-level sums (64 terms per parity)
+
+// B elements of a block: row j + 4t (even slot) and j + 4t + 1 (odd slot),
+// plus 2 rows in the upper lane half; Bm is the m's uniform row base and lo
+// the lane's offset (2 hi 32 + column).
+__device__ __forceinline__ void load_b(const float *__restrict__ Bm, int j, unsigned lo,
+                                       float (&b)[8])
 {
-    if (fmax(fabs(ua), fabs(ub)) > kTwoS) {
-        ua *= kTwoMinusS; ub *= kTwoMinusS;
-        k += 1;
-        f = final_scale(k);
+    const float *__restrict__ Bj = Bm + (long long)j * 32;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        b[2 * t] = Bj[lo + 128 * t];
+        b[2 * t + 1] = Bj[lo + 128 * t + 32];
     }
 }
 
-constexpr int kBlk = 16;  // l-steps per unrolled block (4 MFMA steps)
+// One block of 16 l-steps j..j+15, all inside the m's range.
+template <bool MASK>
+__device__ __forceinline__ void block16(double x, double &ua, double &ub,
+                                        const double *__restrict__ Aj, const float (&b)[8],
+                                        bool live, MfmaTiles &acc)
+{
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const double u0 = fma(Aj[4 * t] * x, ub, -ua);
+        const double u1 = fma(Aj[4 * t + 1] * x, u0, -ub);
+        const double u2 = fma(Aj[4 * t + 2] * x, u1, -u0);
+        const double u3 = fma(Aj[4 * t + 3] * x, u2, -u1);
+        ua = u2;
+        ub = u3;
+        if (MASK)
+            mfma4(opnd(u0, live), opnd(u1, live), opnd(u2, live), opnd(u3, live), b[2 * t],
+                  b[2 * t + 1], acc);
+        else
+            mfma4((float)u0, (float)u1, (float)u2, (float)u3, b[2 * t], b[2 * t + 1], acc);
+    }
+}
+
+// kSuper blocks from j with the B rows in registers one block ahead
+// (alternating sets); on entry ba holds block 0's rows, on exit the rows of
+// block jnext.  MASK: some lane still has k < 0.
+template <bool MASK>
+__device__ __forceinline__ void super_block(double x, double &ua, double &ub, int &k,
+                                            const double *__restrict__ Am,
+                                            const float *__restrict__ Bm, unsigned lo, int j,
+                                            int jnext, float (&ba)[8], float (&bb)[8],
+                                            MfmaTiles &acc)
+{
+#pragma unroll
+    for (int q = 0; q < kSuper; ++q) {
+        float(&cur)[8] = (q & 1) ? bb : ba;
+        float(&nxt)[8] = (q & 1) ? ba : bb;
+        load_b(Bm, (q + 1 < kSuper) ? j + kBlk * (q + 1) : jnext, lo, nxt);
+        const bool live = !MASK || k == 0;
+        block16<MASK>(x, ua, ub, Am + j + kBlk * q, cur, live, acc);
+        if (MASK) rescale_mixed(ua, ub, k);
+    }
+}
+
+__device__ __forceinline__ void add_tiles(MfmaTiles &tot, const MfmaTiles &acc)
+{
+    tot.e0 += acc.e0; tot.e1 += acc.e1; tot.o0 += acc.o0; tot.o1 += acc.o1;
+}
 
 __device__ void mfma_one_m(double x, double s, int m, int i, long long off, double mum,
                            int lmax, const double *__restrict__ A, const float *__restrict__ Bg,
@@ -108,112 +177,82 @@ __device__ void mfma_one_m(double x, double s, int m, int i, long long off, doub
     const int hi = lane >> 5;
     const int col = lane & 31;
     const double *__restrict__ Am = A + off;
-    // lane's B element of row l: Bl[l * 32]; its K slot adds 2 rows in the upper half
-    const float *__restrict__ Bl = Bg + off * 32 + 2 * hi * 32 + col;
+    // row l of the m's B block: Bm[l * 32 + column]; a lane's K slot adds 2
+    // rows in the upper half
+    const float *__restrict__ Bm = Bg + off * 32;
+    const unsigned lo = (unsigned)(2 * hi * 32 + col);
 
     double ua, ub;
     int k;
     seed_mm(mum, s, m, ua, k);
-    double f = final_scale(k);
     ub = (len >= 2) ? (Am[1] * x) * ua : 0.0;
 
     MfmaTiles acc, tot;
-    acc.e0 = v16f{}; acc.e1 = v16f{}; acc.o0 = v16f{}; acc.o1 = v16f{};
-    tot = acc;
 
-    // ---- j = 0..3 (seeds), guarded
+    // ---- j = 0..3 (seeds), guarded; its sums start the second level
     {
-        const float X0 = tof(ua, f);
-        const float X1 = (len > 1) ? tof(ub, f) : 0.0f;
+        const bool live = (k == 0);
         const double A2 = (2 < len) ? Am[2] : 0.0;
         const double u2 = fma(A2 * x, ub, -ua);
         const double A3 = (3 < len) ? Am[3] : 0.0;
         const double u3 = fma(A3 * x, u2, -ub);
-        const float X2 = (2 < len) ? tof(u2, f) : 0.0f;
-        const float X3 = (3 < len) ? tof(u3, f) : 0.0f;
+        const float X0 = opnd(ua, live);
+        const float X1 = (len > 1) ? opnd(ub, live) : 0.0f;
+        const float X2 = (2 < len) ? opnd(u2, live) : 0.0f;
+        const float X3 = (3 < len) ? opnd(u3, live) : 0.0f;
         ua = u2; ub = u3;
-        const float BE = (2 * hi < len) ? Bl[0] : 0.0f;
-        const float BO = (1 + 2 * hi < len) ? Bl[32] : 0.0f;
-        float A0E, A1E, A0O, A1O;
-        swap_halves(X0, X2, A0E, A1E);
-        swap_halves(X1, X3, A0O, A1O);
-        acc.e0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0E, BE, acc.e0, 0, 0, 0);
-        acc.e1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1E, BE, acc.e1, 0, 0, 0);
-        acc.o0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0O, BO, acc.o0, 0, 0, 0);
-        acc.o1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1O, BO, acc.o1, 0, 0, 0);
+        const float BE = (2 * hi < len) ? Bm[lo] : 0.0f;
+        const float BO = (1 + 2 * hi < len) ? Bm[lo + 32] : 0.0f;
+        tot.e0 = v16f{}; tot.e1 = v16f{}; tot.o0 = v16f{}; tot.o1 = v16f{};
+        mfma4(X0, X1, X2, X3, BE, BO, tot);
+    }
+    acc.e0 = v16f{}; acc.e1 = v16f{}; acc.o0 = v16f{}; acc.o1 = v16f{};
+
+    // ---- super-blocks of kSuper x kBlk steps; the first-level sums start
+    // from zero in each and are added into tot at its end
+    int j = 4;
+    bool mask = wave_any(k < 0);
+    float ba[8], bb[8];
+    if (j + kSuper * kBlk <= len) {
+        load_b(Bm, j, lo, ba);
+        while (true) {
+            const int jn = j + kSuper * kBlk;
+            const bool more = jn + kSuper * kBlk <= len;
+            // the prefetch after the last block stays inside the m's range
+            const int jnext = more ? jn : j;
+            if (mask) {
+                super_block<true>(x, ua, ub, k, Am, Bm, lo, j, jnext, ba, bb, acc);
+                mask = wave_any(k < 0);
+            } else {
+                super_block<false>(x, ua, ub, k, Am, Bm, lo, j, jnext, ba, bb, acc);
+            }
+            add_tiles(tot, acc);
+            acc.e0 = v16f{}; acc.e1 = v16f{}; acc.o0 = v16f{}; acc.o1 = v16f{};
+            j = jn;
+            if (!more) break;
+        }
     }
 
-    // ---- unrolled blocks of kBlk steps; the B operands of the next block are
-    // loaded while the current one computes (two register sets, alternating)
-    int j = 4;
-    int blk = 0;
+    // ---- remaining whole blocks (fewer than kSuper)
     if (j + kBlk <= len) {
-        float bx[8], by[8];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            bx[2 * t] = Bl[(long long)(j + 4 * t) * 32];
-            bx[2 * t + 1] = Bl[(long long)(j + 4 * t + 1) * 32];
-        }
+        load_b(Bm, j, lo, ba);
         while (true) {
-            // block on bx, prefetch into by
-            {
-                const int jn = j + kBlk;
-                const bool more = jn + kBlk <= len;
-                {
-                    // unconditional (clamped into the m's range) so that the
-                    // wait counts stay static; unused when !more
-                    const int jl = more ? jn : j;
+            const int jn = j + kBlk;
+            const bool more = jn + kBlk <= len;
+            load_b(Bm, more ? jn : j, lo, bb);
+            const bool live = (k == 0);
+            block16<true>(x, ua, ub, Am + j, ba, live, acc);
+            rescale_mixed(ua, ub, k);
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        by[2 * t] = Bl[(long long)(jl + 4 * t) * 32];
-                        by[2 * t + 1] = Bl[(long long)(jl + 4 * t + 1) * 32];
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    mfma_step4(x, f, ua, ub, Am[j + 4 * t], Am[j + 4 * t + 1], Am[j + 4 * t + 2],
-                               Am[j + 4 * t + 3], bx[2 * t], bx[2 * t + 1], acc);
-                    if (t & 1) rescale_check(ua, ub, k, f);
-                }
-                if (++blk % (kMfmaBlockIters / 4) == 0) {
-                    tot.e0 += acc.e0; tot.e1 += acc.e1; tot.o0 += acc.o0; tot.o1 += acc.o1;
-                    acc.e0 = v16f{}; acc.e1 = v16f{}; acc.o0 = v16f{}; acc.o1 = v16f{};
-                }
-                j = jn;
-                if (!more) break;
-            }
-            // block on by, prefetch into bx
-            {
-                const int jn = j + kBlk;
-                const bool more = jn + kBlk <= len;
-                {
-                    // unconditional (clamped into the m's range) so that the
-                    // wait counts stay static; unused when !more
-                    const int jl = more ? jn : j;
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        bx[2 * t] = Bl[(long long)(jl + 4 * t) * 32];
-                        bx[2 * t + 1] = Bl[(long long)(jl + 4 * t + 1) * 32];
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    mfma_step4(x, f, ua, ub, Am[j + 4 * t], Am[j + 4 * t + 1], Am[j + 4 * t + 2],
-                               Am[j + 4 * t + 3], by[2 * t], by[2 * t + 1], acc);
-                    if (t & 1) rescale_check(ua, ub, k, f);
-                }
-                if (++blk % (kMfmaBlockIters / 4) == 0) {
-                    tot.e0 += acc.e0; tot.e1 += acc.e1; tot.o0 += acc.o0; tot.o1 += acc.o1;
-                    acc.e0 = v16f{}; acc.e1 = v16f{}; acc.o0 = v16f{}; acc.o1 = v16f{};
-                }
-                j = jn;
-                if (!more) break;
-            }
+            for (int t = 0; t < 8; ++t) ba[t] = bb[t];
+            j = jn;
+            if (!more) break;
         }
     }
 
     // ---- tail, guarded
     for (; j < len; j += 4) {
+        const bool live = (k == 0);
         const double A0 = Am[j];
         const double A1 = (j + 1 < len) ? Am[j + 1] : 0.0;
         const double A2 = (j + 2 < len) ? Am[j + 2] : 0.0;
@@ -222,23 +261,17 @@ __device__ void mfma_one_m(double x, double s, int m, int i, long long off, doub
         const double u1 = fma(A1 * x, u0, -ub);
         const double u2 = fma(A2 * x, u1, -u0);
         const double u3 = fma(A3 * x, u2, -u1);
-        const float X0 = tof(u0, f);
-        const float X1 = (j + 1 < len) ? tof(u1, f) : 0.0f;
-        const float X2 = (j + 2 < len) ? tof(u2, f) : 0.0f;
-        const float X3 = (j + 3 < len) ? tof(u3, f) : 0.0f;
+        const float X0 = opnd(u0, live);
+        const float X1 = (j + 1 < len) ? opnd(u1, live) : 0.0f;
+        const float X2 = (j + 2 < len) ? opnd(u2, live) : 0.0f;
+        const float X3 = (j + 3 < len) ? opnd(u3, live) : 0.0f;
         ua = u2; ub = u3;
-        rescale_check(ua, ub, k, f);
-        const float BE = (j + 2 * hi < len) ? Bl[(long long)j * 32] : 0.0f;
-        const float BO = (j + 1 + 2 * hi < len) ? Bl[(long long)(j + 1) * 32] : 0.0f;
-        float A0E, A1E, A0O, A1O;
-        swap_halves(X0, X2, A0E, A1E);
-        swap_halves(X1, X3, A0O, A1O);
-        acc.e0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0E, BE, acc.e0, 0, 0, 0);
-        acc.e1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1E, BE, acc.e1, 0, 0, 0);
-        acc.o0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0O, BO, acc.o0, 0, 0, 0);
-        acc.o1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1O, BO, acc.o1, 0, 0, 0);
+        rescale_mixed(ua, ub, k);
+        const float BE = (j + 2 * hi < len) ? Bm[(long long)j * 32 + lo] : 0.0f;
+        const float BO = (j + 1 + 2 * hi < len) ? Bm[(long long)j * 32 + lo + 32] : 0.0f;
+        mfma4(X0, X1, X2, X3, BE, BO, acc);
     }
-    tot.e0 += acc.e0; tot.e1 += acc.e1; tot.o0 += acc.o0; tot.o1 += acc.o1;
+    add_tiles(tot, acc);
 
     // D layout of the 32x32 tile: column = lane % 32, row = 8 (r/4) + 4 (lane/32) + r % 4
     const int map = grp * 16 + (col >> 1);
