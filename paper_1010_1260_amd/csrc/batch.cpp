@@ -167,14 +167,14 @@ sht_status sht_plan_batch(sht_batch_t *out, const sht_plan_t *plans, int32_t n)
     // Fourier work items per ring size class, longest rings first
     for (int c = 0; c < sht::kNumRingClasses && st == SHT_OK; ++c) {
         std::vector<int2> items;
-        int need = 0;
+        sht::RingLds lds = {};
         std::vector<std::pair<int, int2>> keyed;
         for (int i = 0; i < n; ++i) {
             const sht_plan_s *p = plans[i];
             for (int r = 0; r < p->nrings; ++r)
                 if (p->ring_class[r] == c) {
                     keyed.push_back({p->ring_need[r], make_int2(i, r)});
-                    need = std::max(need, p->ring_need[r]);
+                    sht::ring_lds_add(lds, c, p->ring_n[r], p->ring_nb[r], p->ring_need[r]);
                 }
         }
         std::stable_sort(keyed.begin(), keyed.end(),
@@ -183,7 +183,7 @@ sht_status sht_plan_batch(sht_batch_t *out, const sht_plan_t *plans, int32_t n)
                          });
         for (auto &kv : keyed) items.push_back(kv.second);
         b->cls[c].count = (int)items.size();
-        b->cls[c].fft_entries = need;
+        b->cls[c].lds = lds;
         if (!items.empty() &&
             (hipMalloc((void **)&b->cls[c].d_items, items.size() * sizeof(int2)) != hipSuccess ||
              hipMemcpy(b->cls[c].d_items, items.data(), items.size() * sizeof(int2),

@@ -18,10 +18,18 @@
 // one v_permlane32_swap of (X0, X2) yields the even-parity fragments of both
 // row halves ([X0_lo | X2_lo] and [X0_hi | X2_hi]); (X1, X3) gives the odd ones.
 //
+// Work split.  A workgroup of four waves takes 256 ring pairs and an m-pair
+// (m, mmax - m).  Per super-block of 128 l-rows the coefficients A_l (FP64)
+// and the B rows (FP32, packed per 16-row block so that each lane reads its 8
+// values as two 16-byte words) are copied once into LDS for all four waves
+// (double-buffered, one barrier per super-block); while a wave computes block
+// q of a super-block, block q of the next one is in flight from global memory
+// to LDS, so the recurrence loop never waits on global memory.
+//
 // Accumulation.  FP32 accumulation over all l-terms loses up to ~1e-6; the
-// matrix core accumulates 64 same-parity terms per block, and the block sums
-// are added into a second FP32 accumulator (two-level summation).  Emulated
-// error of Delta at l_max = 4096: about 1.2e-7 relative.
+// matrix core accumulates the 64 same-parity terms of a super-block from zero
+// and the block sums are added into a second FP32 accumulator (two-level
+// summation).  Emulated error of Delta at l_max = 4096: about 1.2e-7 relative.
 #include "recurrence.h"
 #include "sht_internal.h"
 
@@ -29,26 +37,56 @@ namespace sht {
 namespace {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 
+constexpr int kWaves = 4;                   // waves (64 ring pairs each) sharing an m
+constexpr int kThreads = 64 * kWaves;
+constexpr int kBlk = 16;                    // l-rows per block
+constexpr int kBlkFloats = 64 * 8;          // packed block: [lane 64][slot 8]
+constexpr int kSuper = 8;                   // blocks per super-block: 64 terms per parity
+constexpr int kSuperRows = kSuper * kBlk;
+constexpr int kABytes = kSuperRows * 8;     // A of a super-block in LDS
+constexpr int kBufBytes = kABytes + kSuper * kBlkFloats * 4;
 
-__global__ void k_prescale_f32(const double2 *__restrict__ alm, const double *__restrict__ cn,
-                               float *__restrict__ Bf, long long nalm, int nmaps, long long m0len)
+// Packed B: slot s = 2t + p of lane (hi, col) in block b of an m holds row
+// 16 b + 4 t + 2 hi + p (p = 0: even slot, 1: odd slot) of column col, i.e.
+// a'_lm = c_lm a_lm of map col / 2 (Re for even col, Im for odd), zero past
+// the m's last row.  One workgroup per block (its m found once), two floats
+// per thread.
+__global__ __launch_bounds__(256) void k_prescale_f32(
+    const double2 *__restrict__ alm, const double *__restrict__ cn,
+    const long long *__restrict__ moff, const int *__restrict__ mval,
+    const long long *__restrict__ boff16, int nm, int lmax, long long nalm, long long nblocks,
+    int nmaps, long long m0len, float *__restrict__ Bp)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nalm * 32) return;
-    const long long e = t >> 5;
-    const int col = (int)(t & 31);
+    const long long blk = blockIdx.x;
     const int grp = blockIdx.y;
-    const int map = grp * 16 + (col >> 1);
-    float v = 0.0f;
-    if (map < nmaps) {
-        const double2 a = alm[(long long)map * nalm + e];
-        const double c = cn[e];
-        const double x = (col & 1) ? ((e < m0len) ? 0.0 : a.y * c) : a.x * c;
-        v = (float)x;
+    int lo = 0, hh = nm - 1;
+    while (lo < hh) {
+        const int mid = (lo + hh + 1) >> 1;
+        if (boff16[mid] <= blk) lo = mid; else hh = mid - 1;
     }
-    Bf[((long long)grp * nalm + e) * 32 + col] = v;
+    const int i = lo;
+    const int len = lmax - mval[i] + 1;
+    const long long row0 = (blk - boff16[i]) * kBlk;
+    float *__restrict__ out = Bp + ((long long)grp * nblocks + blk) * kBlkFloats;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int w = threadIdx.x + 256 * h;
+        const int lane = w >> 3, slot = w & 7;
+        const int hi = lane >> 5, col = lane & 31;
+        const long long row = row0 + 4 * (slot >> 1) + 2 * hi + (slot & 1);
+        const int map = grp * 16 + (col >> 1);
+        float v = 0.0f;
+        if (row < len && map < nmaps) {
+            const long long e = moff[i] + row;
+            const double2 a = alm[(long long)map * nalm + e];
+            const double c = cn[e];
+            v = (float)((col & 1) ? ((e < m0len) ? 0.0 : a.y * c) : a.x * c);
+        }
+        out[w] = v;
+    }
 }
 
 // Lane state of the mixed kernels.  u = P_l / c_l is carried as v 2^(512 k),
@@ -88,6 +126,16 @@ struct MfmaTiles {
     v16f e0, e1, o0, o1;  // even / odd parity, rows 0-31 / 32-63
 };
 
+__device__ __forceinline__ void zero_tiles(MfmaTiles &t)
+{
+    t.e0 = v16f{}; t.e1 = v16f{}; t.o0 = v16f{}; t.o1 = v16f{};
+}
+
+__device__ __forceinline__ void add_tiles(MfmaTiles &tot, const MfmaTiles &acc)
+{
+    tot.e0 += acc.e0; tot.e1 += acc.e1; tot.o0 += acc.o0; tot.o1 += acc.o1;
+}
+
 // Four MFMAs of one group of 4 l-values: X0..X3 = P_l..P_{l+3} of the lane's
 // ring pair; BE / BO = the lane's B elements of the even / odd rows.
 __device__ __forceinline__ void mfma4(float X0, float X1, float X2, float X3, float BE, float BO,
@@ -102,35 +150,34 @@ __device__ __forceinline__ void mfma4(float X0, float X1, float X2, float X3, fl
     acc.o1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1O, BO, acc.o1, 0, 0, 0);
 }
 
-constexpr int kBlk = 16;    // l-steps per block (4 groups of 4)
-constexpr int kSuper = 8;   // blocks per flush of the first-level sums (64 terms per parity)
-
-// B elements of a block: row j + 4t (even slot) and j + 4t + 1 (odd slot),
-// plus 2 rows in the upper lane half; Bm is the m's uniform row base and lo
-// the lane's offset (2 hi 32 + column).
-__device__ __forceinline__ void load_b(const float *__restrict__ Bm, int j, unsigned lo,
-                                       float (&b)[8])
-{
-    const float *__restrict__ Bj = Bm + (long long)j * 32;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        b[2 * t] = Bj[lo + 128 * t];
-        b[2 * t + 1] = Bj[lo + 128 * t + 32];
-    }
-}
-
-// One block of 16 l-steps j..j+15, all inside the m's range.
-template <bool MASK>
+// One block of 16 l-rows from LDS: Ab = its 16 coefficients, Bb = the lane's
+// 8 packed B values.  SEED: the block holds rows 0..15 of the m, whose first
+// group starts the recurrence from P_mm (ua) with P_{m+1,m} = A_1 x P_mm.
+// Rows past the m's last one have A = 0 and B = 0 and contribute nothing.
+template <bool MASK, bool SEED>
 __device__ __forceinline__ void block16(double x, double &ua, double &ub,
-                                        const double *__restrict__ Aj, const float (&b)[8],
-                                        bool live, MfmaTiles &acc)
+                                        const double2 *__restrict__ Ab,
+                                        const v4f *__restrict__ Bb, bool live, MfmaTiles &acc)
 {
+    double2 a[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) a[t] = Ab[t];
+    const v4f b03 = Bb[0], b47 = Bb[1];
+    const float b[8] = {b03.x, b03.y, b03.z, b03.w, b47.x, b47.y, b47.z, b47.w};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const double u0 = fma(Aj[4 * t] * x, ub, -ua);
-        const double u1 = fma(Aj[4 * t + 1] * x, u0, -ub);
-        const double u2 = fma(Aj[4 * t + 2] * x, u1, -u0);
-        const double u3 = fma(Aj[4 * t + 3] * x, u2, -u1);
+        const double2 a01 = a[2 * t], a23 = a[2 * t + 1];
+        double u0, u1;
+        if (SEED && t == 0) {
+            u0 = ua;
+            u1 = (a01.y * x) * ua;
+            ub = u1;
+        } else {
+            u0 = fma(a01.x * x, ub, -ua);
+            u1 = fma(a01.y * x, u0, -ub);
+        }
+        const double u2 = fma(a23.x * x, u1, -u0);
+        const double u3 = fma(a23.y * x, u2, -u1);
         ua = u2;
         ub = u3;
         if (MASK)
@@ -141,141 +188,125 @@ __device__ __forceinline__ void block16(double x, double &ua, double &ub,
     }
 }
 
-// kSuper blocks from j with the B rows in registers one block ahead
-// (alternating sets); on entry ba holds block 0's rows, on exit the rows of
-// block jnext.  MASK: some lane still has k < 0.
-template <bool MASK>
-__device__ __forceinline__ void super_block(double x, double &ua, double &ub, int &k,
-                                            const double *__restrict__ Am,
-                                            const float *__restrict__ Bm, unsigned lo, int j,
-                                            int jnext, float (&ba)[8], float (&bb)[8],
-                                            MfmaTiles &acc)
+// A thread's share of one block of the next super-block in flight
+// (global -> registers -> LDS): 8 bytes of packed B, and for threads 0-7 two
+// coefficients.
+struct Stage {
+    float2 b;
+    double2 a;
+};
+
+__device__ __forceinline__ void stage_load(Stage &g, const float *__restrict__ Bm, int nblk,
+                                           const double *__restrict__ Am, int len, int sb, int q,
+                                           int tid)
 {
-#pragma unroll
-    for (int q = 0; q < kSuper; ++q) {
-        float(&cur)[8] = (q & 1) ? bb : ba;
-        float(&nxt)[8] = (q & 1) ? ba : bb;
-        load_b(Bm, (q + 1 < kSuper) ? j + kBlk * (q + 1) : jnext, lo, nxt);
-        const bool live = !MASK || k == 0;
-        block16<MASK>(x, ua, ub, Am + j + kBlk * q, cur, live, acc);
-        if (MASK) rescale_mixed(ua, ub, k);
+    const int blk = sb * kSuper + q;
+    g.b = (blk < nblk)
+              ? reinterpret_cast<const float2 *>(Bm + (long long)blk * kBlkFloats)[tid]
+              : make_float2(0.0f, 0.0f);
+    if (tid < kBlk / 2) {
+        const int r = blk * kBlk + 2 * tid;
+        g.a.x = (r < len) ? Am[r] : 0.0;
+        g.a.y = (r + 1 < len) ? Am[r + 1] : 0.0;
     }
 }
 
-__device__ __forceinline__ void add_tiles(MfmaTiles &tot, const MfmaTiles &acc)
+__device__ __forceinline__ void stage_store(const Stage &g, char *buf, int q, int tid)
 {
-    tot.e0 += acc.e0; tot.e1 += acc.e1; tot.o0 += acc.o0; tot.o1 += acc.o1;
+    reinterpret_cast<float2 *>(buf + kABytes + q * kBlkFloats * 4)[tid] = g.b;
+    if (tid < kBlk / 2) reinterpret_cast<double2 *>(buf)[q * (kBlk / 2) + tid] = g.a;
 }
 
-__device__ void mfma_one_m(double x, double s, int m, int i, long long off, double mum,
-                           int lmax, const double *__restrict__ A, const float *__restrict__ Bg,
+// The blocks of super-block sb, held in LDS buffer `cur`, while block q of
+// super-block sb + 1 is copied into `nxt` (when `more`); the first-level sums
+// start from zero and are added into tot at the end.
+template <bool MASK>
+__device__ __forceinline__ void super_compute(double x, double &ua, double &ub, int &k,
+                                              const char *cur, char *nxt, bool more, int sb,
+                                              int nb, bool seed, const float *__restrict__ Bm,
+                                              int nblk, const double *__restrict__ Am, int len,
+                                              int tid, MfmaTiles &acc, MfmaTiles &tot)
+{
+    const int lane = tid & 63;
+    const double2 *As = reinterpret_cast<const double2 *>(cur);
+    const v4f *Bs = reinterpret_cast<const v4f *>(cur + kABytes) + lane * 2;
+    Stage g;
+    zero_tiles(acc);
+    if (more) stage_load(g, Bm, nblk, Am, len, sb + 1, 0, tid);
+    __builtin_amdgcn_sched_barrier(0);
+    if (seed)
+        block16<true, true>(x, ua, ub, As, Bs, k == 0, acc);
+    else
+        block16<MASK, false>(x, ua, ub, As, Bs, !MASK || k == 0, acc);
+    if (MASK || seed) rescale_mixed(ua, ub, k);
+    if (more) stage_store(g, nxt, 0, tid);
+    for (int q = 1; q < nb; ++q) {
+        if (more) stage_load(g, Bm, nblk, Am, len, sb + 1, q, tid);
+        __builtin_amdgcn_sched_barrier(0);
+        block16<MASK, false>(x, ua, ub, As + (kBlk / 2) * q, Bs + (kBlkFloats / 4) * q,
+                             !MASK || k == 0, acc);
+        if (MASK) rescale_mixed(ua, ub, k);
+        if (more) stage_store(g, nxt, q, tid);
+    }
+    add_tiles(tot, acc);
+}
+
+// One m for the workgroup's 4 x 64 ring pairs.  Every thread runs the same
+// number of super-blocks and barriers.
+__device__ void mfma_one_m(char (*lds)[kBufBytes], double x, double s, int m, int i,
+                           long long off, long long boffi, double mum, int lmax,
+                           const double *__restrict__ A, const float *__restrict__ Bg,
                            double *__restrict__ delta, const PairDesc *__restrict__ pairs,
                            int npairs, int pb, int grp, int nmaps, int nrings, int nm)
 {
-    const int len = lmax - m + 1;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
     const int hi = lane >> 5;
     const int col = lane & 31;
+    const int len = lmax - m + 1;
+    const int nblk = (len + kBlk - 1) / kBlk;
+    const int nsb = (nblk + kSuper - 1) / kSuper;
     const double *__restrict__ Am = A + off;
-    // row l of the m's B block: Bm[l * 32 + column]; a lane's K slot adds 2
-    // rows in the upper half
-    const float *__restrict__ Bm = Bg + off * 32;
-    const unsigned lo = (unsigned)(2 * hi * 32 + col);
+    const float *__restrict__ Bm = Bg + boffi * kBlkFloats;
 
-    double ua, ub;
+    // first super-block: copied before the loop (a super-block with a
+    // successor always has kSuper blocks)
+    {
+        const int nb0 = min(kSuper, nblk);
+        for (int q = 0; q < nb0; ++q) {
+            Stage g;
+            stage_load(g, Bm, nblk, Am, len, 0, q, tid);
+            stage_store(g, lds[0], q, tid);
+        }
+    }
+    __syncthreads();
+
+    double ua, ub = 0.0;
     int k;
     seed_mm(mum, s, m, ua, k);
-    ub = (len >= 2) ? (Am[1] * x) * ua : 0.0;
 
     MfmaTiles acc, tot;
-
-    // ---- j = 0..3 (seeds), guarded; its sums start the second level
-    {
-        const bool live = (k == 0);
-        const double A2 = (2 < len) ? Am[2] : 0.0;
-        const double u2 = fma(A2 * x, ub, -ua);
-        const double A3 = (3 < len) ? Am[3] : 0.0;
-        const double u3 = fma(A3 * x, u2, -ub);
-        const float X0 = opnd(ua, live);
-        const float X1 = (len > 1) ? opnd(ub, live) : 0.0f;
-        const float X2 = (2 < len) ? opnd(u2, live) : 0.0f;
-        const float X3 = (3 < len) ? opnd(u3, live) : 0.0f;
-        ua = u2; ub = u3;
-        const float BE = (2 * hi < len) ? Bm[lo] : 0.0f;
-        const float BO = (1 + 2 * hi < len) ? Bm[lo + 32] : 0.0f;
-        tot.e0 = v16f{}; tot.e1 = v16f{}; tot.o0 = v16f{}; tot.o1 = v16f{};
-        mfma4(X0, X1, X2, X3, BE, BO, tot);
-    }
-    acc.e0 = v16f{}; acc.e1 = v16f{}; acc.o0 = v16f{}; acc.o1 = v16f{};
-
-    // ---- super-blocks of kSuper x kBlk steps; the first-level sums start
-    // from zero in each and are added into tot at its end
-    int j = 4;
-    bool mask = wave_any(k < 0);
-    float ba[8], bb[8];
-    if (j + kSuper * kBlk <= len) {
-        load_b(Bm, j, lo, ba);
-        while (true) {
-            const int jn = j + kSuper * kBlk;
-            const bool more = jn + kSuper * kBlk <= len;
-            // the prefetch after the last block stays inside the m's range
-            const int jnext = more ? jn : j;
-            if (mask) {
-                super_block<true>(x, ua, ub, k, Am, Bm, lo, j, jnext, ba, bb, acc);
-                mask = wave_any(k < 0);
-            } else {
-                super_block<false>(x, ua, ub, k, Am, Bm, lo, j, jnext, ba, bb, acc);
-            }
-            add_tiles(tot, acc);
-            acc.e0 = v16f{}; acc.e1 = v16f{}; acc.o0 = v16f{}; acc.o1 = v16f{};
-            j = jn;
-            if (!more) break;
+    zero_tiles(tot);
+    bool mask = true;  // the seed super-block runs masked
+    for (int sb = 0; sb < nsb; ++sb) {
+        const bool more = sb + 1 < nsb;
+        const char *cur = lds[sb & 1];
+        char *nxt = lds[(sb + 1) & 1];
+        const int nb = min(kSuper, nblk - sb * kSuper);
+        if (mask) {
+            super_compute<true>(x, ua, ub, k, cur, nxt, more, sb, nb, sb == 0, Bm, nblk, Am, len,
+                                tid, acc, tot);
+            mask = wave_any(k < 0);
+        } else {
+            super_compute<false>(x, ua, ub, k, cur, nxt, more, sb, nb, false, Bm, nblk, Am, len,
+                                 tid, acc, tot);
         }
+        __syncthreads();
     }
-
-    // ---- remaining whole blocks (fewer than kSuper)
-    if (j + kBlk <= len) {
-        load_b(Bm, j, lo, ba);
-        while (true) {
-            const int jn = j + kBlk;
-            const bool more = jn + kBlk <= len;
-            load_b(Bm, more ? jn : j, lo, bb);
-            const bool live = (k == 0);
-            block16<true>(x, ua, ub, Am + j, ba, live, acc);
-            rescale_mixed(ua, ub, k);
-#pragma unroll
-            for (int t = 0; t < 8; ++t) ba[t] = bb[t];
-            j = jn;
-            if (!more) break;
-        }
-    }
-
-    // ---- tail, guarded
-    for (; j < len; j += 4) {
-        const bool live = (k == 0);
-        const double A0 = Am[j];
-        const double A1 = (j + 1 < len) ? Am[j + 1] : 0.0;
-        const double A2 = (j + 2 < len) ? Am[j + 2] : 0.0;
-        const double A3 = (j + 3 < len) ? Am[j + 3] : 0.0;
-        const double u0 = fma(A0 * x, ub, -ua);
-        const double u1 = fma(A1 * x, u0, -ub);
-        const double u2 = fma(A2 * x, u1, -u0);
-        const double u3 = fma(A3 * x, u2, -u1);
-        const float X0 = opnd(u0, live);
-        const float X1 = (j + 1 < len) ? opnd(u1, live) : 0.0f;
-        const float X2 = (j + 2 < len) ? opnd(u2, live) : 0.0f;
-        const float X3 = (j + 3 < len) ? opnd(u3, live) : 0.0f;
-        ua = u2; ub = u3;
-        rescale_mixed(ua, ub, k);
-        const float BE = (j + 2 * hi < len) ? Bm[(long long)j * 32 + lo] : 0.0f;
-        const float BO = (j + 1 + 2 * hi < len) ? Bm[(long long)j * 32 + lo + 32] : 0.0f;
-        mfma4(X0, X1, X2, X3, BE, BO, acc);
-    }
-    add_tiles(tot, acc);
 
     // D layout of the 32x32 tile: column = lane % 32, row = 8 (r/4) + 4 (lane/32) + r % 4
     const int map = grp * 16 + (col >> 1);
-    if (map >= nmaps) return;
+    if (map >= nmaps) return;  // no barrier follows in this m
     const int part = col & 1;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -296,30 +327,35 @@ __device__ void mfma_one_m(double x, double s, int m, int i, long long off, doub
     }
 }
 
-__global__ __launch_bounds__(64) void k_legendre_mfma_f32(
-    const PairDesc *__restrict__ pairs, int npairs, int pblocks,
+__global__ __launch_bounds__(kThreads, 2) void k_legendre_mfma_f32(
+    const PairDesc *__restrict__ pairs, int npairs, int pgroups,
     const int *__restrict__ mval, const long long *__restrict__ moff,
-    const double *__restrict__ mu, int nm, int nmpairs, int lmax,
-    const double *__restrict__ A, const float *__restrict__ Bf, long long nalm,
+    const long long *__restrict__ boff16, const double *__restrict__ mu, int nm, int nmpairs,
+    int lmax, const double *__restrict__ A, const float *__restrict__ Bp, long long nblocks,
     double *__restrict__ delta, int nrings, int nmaps, long long total)
 {
+    __shared__ __attribute__((aligned(16))) char lds[2][kBufBytes];
     const long long L = xcd_logical(blockIdx.x, total);
-    const int pb = (int)(L % pblocks);
-    const long long rest = L / pblocks;
+    const int pg = (int)(L % pgroups);
+    const long long rest = L / pgroups;
     const int q = (int)(rest % nmpairs);
     const int grp = (int)(rest / nmpairs);
-    const int p = pb * 64 + threadIdx.x;
+    const int pb = pg * kWaves + (int)(threadIdx.x >> 6);
+    const int p = pb * 64 + (int)(threadIdx.x & 63);
     double x = 0.0, s = 0.0;
     if (p < npairs) {
         const PairDesc d = pairs[p];
         x = d.x; s = d.s;
     }
-    const float *Bg = Bf + (long long)grp * nalm * 32;
+    const float *Bg = Bp + (long long)grp * nblocks * kBlkFloats;
+    // the second m of the pair (if any) is taken by every thread of the
+    // workgroup, so the barrier count stays uniform; the last barrier of the
+    // first m orders its LDS reads before the second m's first copy
     for (int t = 0; t < 2; ++t) {
         const int i = (t == 0) ? q : nm - 1 - q;
         if (t == 1 && i == q) break;
-        mfma_one_m(x, s, mval[i], i, moff[i], mu[i], lmax, A, Bg, delta, pairs, npairs, pb, grp,
-                   nmaps, nrings, nm);
+        mfma_one_m(lds, x, s, mval[i], i, moff[i], boff16[i], mu[i], lmax, A, Bg, delta, pairs,
+                   npairs, pb, grp, nmaps, nrings, nm);
     }
 }
 
@@ -328,33 +364,34 @@ __global__ __launch_bounds__(64) void k_legendre_mfma_f32(
 size_t mfma_bf_bytes(const sht_plan_s *p)
 {
     const size_t groups = (size_t)((p->nmaps + 15) / 16);
-    return groups * (size_t)p->nalm * 32 * sizeof(float);
+    return groups * (size_t)p->nblk16 * kBlkFloats * sizeof(float);
 }
 
-hipError_t launch_prescale_f32(const sht_plan_s *p, const double *alm, float *Bf, hipStream_t st)
+hipError_t launch_prescale_f32(const sht_plan_s *p, const double *alm, float *Bp, hipStream_t st)
 {
     const long long m0len = (p->mval[0] == 0) ? (p->lmax + 1) : 0;
     const int groups = (p->nmaps + 15) / 16;
-    const long long n = p->nalm * 32;
-    dim3 grid((unsigned)((n + 255) / 256), (unsigned)groups);
+    if (p->nblk16 <= 0 || p->nblk16 > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    dim3 grid((unsigned)p->nblk16, (unsigned)groups);
     hipLaunchKernelGGL(k_prescale_f32, grid, dim3(256), 0, st,
-                       reinterpret_cast<const double2 *>(alm), p->d_cn, Bf, p->nalm, p->nmaps,
-                       m0len);
+                       reinterpret_cast<const double2 *>(alm), p->d_cn, p->d_moff, p->d_mval,
+                       p->d_boff16, p->nm, p->lmax, p->nalm, p->nblk16, p->nmaps, m0len, Bp);
     return hipGetLastError();
 }
 
-hipError_t launch_legendre_mfma_f32(const sht_plan_s *p, const float *Bf, double2 *delta,
+hipError_t launch_legendre_mfma_f32(const sht_plan_s *p, const float *Bp, double2 *delta,
                                     hipStream_t st)
 {
     const int pblocks = (p->npairs + 63) / 64;
+    const int pgroups = (pblocks + kWaves - 1) / kWaves;
     const int nmpairs = (p->nm + 1) / 2;
     const int groups = (p->nmaps + 15) / 16;
-    const long long total = (long long)pblocks * nmpairs * groups;
+    const long long total = (long long)pgroups * nmpairs * groups;
     if (total <= 0 || total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_legendre_mfma_f32, dim3((unsigned)total), dim3(64), 0, st, p->d_pairs,
-                       p->npairs, pblocks, p->d_mval, p->d_moff, p->d_mu, p->nm, nmpairs,
-                       p->lmax, p->d_A, Bf, p->nalm, reinterpret_cast<double *>(delta),
-                       p->nrings, p->nmaps, total);
+    hipLaunchKernelGGL(k_legendre_mfma_f32, dim3((unsigned)total), dim3(kThreads), 0, st,
+                       p->d_pairs, p->npairs, pgroups, p->d_mval, p->d_moff, p->d_boff16,
+                       p->d_mu, p->nm, nmpairs, p->lmax, p->d_A, Bp, p->nblk16,
+                       reinterpret_cast<double *>(delta), p->nrings, p->nmaps, total);
     return hipGetLastError();
 }
 

@@ -23,13 +23,21 @@
 // per-length tables computed on the host in extended precision.
 #include "sht_internal.h"
 
+// Every fused multiply-add in this file is written out (fma, cmul): no
+// contraction, so that all instantiations of the Fourier kernels (single and
+// batched, any size class) round identically.
+#pragma clang fp contract(off)
+
 namespace sht {
 namespace {
 
 
+// Complex product with its roundings pinned (one product, then one fused
+// multiply-add per component), so that every inlined copy of a kernel rounds
+// alike whatever the compiler would otherwise contract.
 __device__ inline double2 cmul(double2 a, double2 b)
 {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
 }
 __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
@@ -128,11 +136,35 @@ __device__ inline void small_dft(double2 (&v)[R], int sign)
     }
 }
 
-// One Stockham pass of radix R over n <= MAXN points in LDS.  tw[idx * tws]
-// is e^{+2 pi i idx / n}.  j / Ns is taken as umulhi(j, ceil(2^32 / Ns)),
-// which is exact for j, Ns < 2^13.
+// Twiddles e^{+2 pi i t / L} (t < L <= 16384) from a two-level table in LDS:
+// T[b] = w^b for b < 64 and T[64 + a] = w^(64 a), so w^t = T[64 + t/64] T[t % 64]
+// (within 2 ulp; T[64] = 1 exactly).  Filled from the plan's full table `tab`
+// (entry t at tab[t]) at the start of a workgroup, so that the FFT passes
+// never wait on global memory.
+constexpr int kTwEntries = 64 + 256;
+
+template <int NT>
+__device__ __attribute__((always_inline)) inline void load_tw(double2 *T,
+                                                              const double2 *__restrict__ tab,
+                                                              int L)
+{
+    const int n1 = (L + 63) >> 6;
+    for (int e = threadIdx.x; e < 64 + n1; e += NT) {
+        const int t = (e < 64) ? e : 64 * (e - 64);
+        T[e] = (t < L) ? tab[t] : make_double2(1.0, 0.0);
+    }
+}
+
+__device__ inline double2 tw_at(const double2 *T, int t)
+{
+    return cmul(T[64 + (t >> 6)], T[t & 63]);
+}
+
+// One Stockham pass of radix R over n <= MAXN points in LDS.  T is the LDS
+// table of e^{+2 pi i t / L} with L = n * tws.  j / Ns is taken as
+// umulhi(j, ceil(2^32 / Ns)), which is exact for j, Ns < 2^13.
 template <int R, int NT, int MAXN>
-__device__ __attribute__((always_inline)) inline void fft_pass(double2 *buf, int n, int Ns, int sign, const double2 *__restrict__ tw,
+__device__ __attribute__((always_inline)) inline void fft_pass(double2 *buf, int n, int Ns, int sign, const double2 *T,
                          int tws)
 {
     constexpr int MAXQ = (MAXN / R + NT - 1) / NT;
@@ -147,10 +179,10 @@ __device__ __attribute__((always_inline)) inline void fft_pass(double2 *buf, int
             const int jq = (Ns == 1) ? j : (int)__umulhi((unsigned)j, magic);
             const int k = j - jq * Ns;
             const int ts = tstep0 * k;
-            // twiddles w^r, r = 1..R-1, as powers of one table entry w = tw[ts]
+            // twiddles w^r, r = 1..R-1, as powers of one table entry w
             double2 w1 = make_double2(1.0, 0.0);
             if (ts != 0) {
-                w1 = tw[ts];
+                w1 = tw_at(T, ts);
                 if (sign < 0) w1.y = -w1.y;
             }
             double2 wr = w1;
@@ -182,22 +214,22 @@ __device__ __attribute__((always_inline)) inline void fft_pass(double2 *buf, int
 // In-place DFT of 7-smooth length n <= MAXN:
 // buf_k <- sum_j buf_j e^{sign 2 pi i j k / n}.
 template <int NT, int MAXN>
-__device__ __attribute__((always_inline)) inline void fft_lds(double2 *buf, int n, int sign, const double2 *__restrict__ tw, int tws)
+__device__ __attribute__((always_inline)) inline void fft_lds(double2 *buf, int n, int sign, const double2 *T, int tws)
 {
     int Ns = 1, rem = n;
     while (rem > 1) {
         if (rem % 8 == 0) {
-            fft_pass<8, NT, MAXN>(buf, n, Ns, sign, tw, tws); Ns *= 8; rem /= 8;
+            fft_pass<8, NT, MAXN>(buf, n, Ns, sign, T, tws); Ns *= 8; rem /= 8;
         } else if (rem % 4 == 0) {
-            fft_pass<4, NT, MAXN>(buf, n, Ns, sign, tw, tws); Ns *= 4; rem /= 4;
+            fft_pass<4, NT, MAXN>(buf, n, Ns, sign, T, tws); Ns *= 4; rem /= 4;
         } else if (rem % 2 == 0) {
-            fft_pass<2, NT, MAXN>(buf, n, Ns, sign, tw, tws); Ns *= 2; rem /= 2;
+            fft_pass<2, NT, MAXN>(buf, n, Ns, sign, T, tws); Ns *= 2; rem /= 2;
         } else if (rem % 3 == 0) {
-            fft_pass<3, NT, MAXN>(buf, n, Ns, sign, tw, tws); Ns *= 3; rem /= 3;
+            fft_pass<3, NT, MAXN>(buf, n, Ns, sign, T, tws); Ns *= 3; rem /= 3;
         } else if (rem % 5 == 0) {
-            fft_pass<5, NT, MAXN>(buf, n, Ns, sign, tw, tws); Ns *= 5; rem /= 5;
+            fft_pass<5, NT, MAXN>(buf, n, Ns, sign, T, tws); Ns *= 5; rem /= 5;
         } else {
-            fft_pass<7, NT, MAXN>(buf, n, Ns, sign, tw, tws); Ns *= 7; rem /= 7;
+            fft_pass<7, NT, MAXN>(buf, n, Ns, sign, T, tws); Ns *= 7; rem /= 7;
         }
     }
 }
@@ -205,44 +237,104 @@ __device__ __attribute__((always_inline)) inline void fft_lds(double2 *buf, int 
 // In-place DFT of any length len by Bluestein's algorithm:
 // e^{i 2 pi jk/len} = c_j c_k conj(c_{j-k}), c_k = e^{i pi k^2 / len}, as a
 // cyclic convolution of 7-smooth length nb >= 2 len - 1.
-// chirp[k] = c_k (k < len), twb = e^{2 pi i k / nb}, bq = DFT^-(conj c, wrapped) / nb.
+// ch = this thread's chirps c_k, k = tid + q NT (loaded ahead by the caller),
+// TB = LDS table of e^{2 pi i k / nb}, bq = DFT^-(conj c, wrapped) / nb.
 // A sign -1 transform is conj(DFT^+(conj x)).
-template <int NT, int MAXN>
+// REG: the chirps are held in registers from the start of the workgroup
+// (their load latency overlaps the fold), else read where used.
+template <int NT, int MAXN, bool REG>
+struct Chirps {
+    static constexpr int Q = (MAXN / 2 + NT - 1) / NT;  // len <= (nb + 1) / 2 <= MAXN / 2
+    double2 c[REG ? Q : 1];
+    const double2 *p;
+    __device__ double2 get(int q, int k) const { return REG ? c[REG ? q : 0] : p[k]; }
+};
+
+template <int NT, int MAXN, bool REG>
+__device__ __attribute__((always_inline)) inline void load_chirps(Chirps<NT, MAXN, REG> &ch,
+                                                                  const double2 *__restrict__ chirp,
+                                                                  int len)
+{
+    ch.p = chirp;
+    if (REG) {
+#pragma unroll
+        for (int q = 0; q < Chirps<NT, MAXN, REG>::Q; ++q) {
+            const int k = threadIdx.x + q * NT;
+            ch.c[REG ? q : 0] = (k < len) ? chirp[k] : make_double2(0.0, 0.0);
+        }
+    }
+}
+
+template <int NT, int MAXN, bool REG>
 __device__ __attribute__((always_inline)) inline void bluestein_lds(double2 *buf, int len, int nb, int sign,
-                              const double2 *__restrict__ chirp, const double2 *__restrict__ twb,
+                              const Chirps<NT, MAXN, REG> &ch, const double2 *TB,
                               const double2 *__restrict__ bq)
 {
-    for (int k = threadIdx.x; k < nb; k += NT) {
-        if (k < len) {
-            double2 x = buf[k];
-            if (sign < 0) x.y = -x.y;
-            buf[k] = cmul(x, chirp[k]);
-        } else {
-            buf[k] = make_double2(0.0, 0.0);
+    constexpr int QB = MAXN / NT;
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+        const int k = threadIdx.x + q * NT;
+        if (k < nb) {
+            if (q < Chirps<NT, MAXN, REG>::Q && k < len) {
+                double2 x = buf[k];
+                if (sign < 0) x.y = -x.y;
+                buf[k] = cmul(x, ch.get(q < Chirps<NT, MAXN, REG>::Q ? q : 0, k));
+            } else {
+                buf[k] = make_double2(0.0, 0.0);
+            }
         }
     }
     __syncthreads();
-    fft_lds<NT, MAXN>(buf, nb, -1, twb, 1);
-    for (int k = threadIdx.x; k < nb; k += NT) buf[k] = cmul(buf[k], bq[k]);
+    fft_lds<NT, MAXN>(buf, nb, -1, TB, 1);
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+        const int k = threadIdx.x + q * NT;
+        if (k < nb) buf[k] = cmul(buf[k], bq[k]);
+    }
     __syncthreads();
-    fft_lds<NT, MAXN>(buf, nb, +1, twb, 1);
-    for (int j = threadIdx.x; j < len; j += NT) {
-        double2 z = cmul(buf[j], chirp[j]);
-        if (sign < 0) z.y = -z.y;
-        buf[j] = z;
+    fft_lds<NT, MAXN>(buf, nb, +1, TB, 1);
+#pragma unroll
+    for (int q = 0; q < Chirps<NT, MAXN, REG>::Q; ++q) {
+        const int j = threadIdx.x + q * NT;
+        if (j < len) {
+            double2 z = cmul(buf[j], ch.get(q, j));
+            if (sign < 0) z.y = -z.y;
+            buf[j] = z;
+        }
     }
     __syncthreads();
 }
 
-template <int NT, int MAXN>
-__device__ inline void ring_dft(double2 *buf, const RingDesc &d, int sign,
-                                const double2 *__restrict__ pool)
+// LDS tables of a ring's Fourier step: TW for e^{2 pi i k / n} (n-point
+// roots: the half-length FFT and its pre/post twiddles), TB for the
+// Bluestein length.
+struct RingTables {
+    double2 *TW;
+    double2 *TB;
+};
+
+template <int NT, int MAXN, bool REG>
+__device__ __attribute__((always_inline)) inline void ring_tables_load(const RingTables &rt,
+                                                                       const RingDesc &d,
+                                                                       const double2 *__restrict__ pool,
+                                                                       Chirps<NT, MAXN, REG> &ch)
+{
+    load_tw<NT>(rt.TW, pool + d.tw, d.n);
+    if (d.nb != 0) {
+        load_tw<NT>(rt.TB, pool + d.twb, d.nb);
+        load_chirps<NT, MAXN, REG>(ch, pool + d.tch, d.clen);
+    }
+}
+
+template <int NT, int MAXN, bool REG>
+__device__ __attribute__((always_inline)) inline void ring_dft(double2 *buf, const RingDesc &d, int sign,
+                                const double2 *__restrict__ pool, const RingTables &rt,
+                                const Chirps<NT, MAXN, REG> &ch)
 {
     if (d.nb == 0) {
-        fft_lds<NT, MAXN>(buf, d.clen, sign, pool + d.tw, (d.n % 2 == 0) ? 2 : 1);
+        fft_lds<NT, MAXN>(buf, d.clen, sign, rt.TW, (d.n % 2 == 0) ? 2 : 1);
     } else {
-        bluestein_lds<NT, MAXN>(buf, d.clen, d.nb, sign, pool + d.tch, pool + d.twb,
-                                pool + d.bq);
+        bluestein_lds<NT, MAXN, REG>(buf, d.clen, d.nb, sign, ch, rt.TB, pool + d.bq);
     }
 }
 
@@ -263,14 +355,17 @@ __device__ inline double2 load_mode(const double2 *__restrict__ drow,
 }
 
 // Synthesis: one workgroup per (ring of this size class, map).  LDS: the
-// spectrum / FFT buffer (fft_entries) followed by NT staging slots.
+// spectrum / FFT buffer, the twiddle tables and the alias staging slots
+// (RingLds).
 // Synthesis of one ring: drow = its Delta_m row, out = its first pixel.
-template <int NT, int MAXN>
-__device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, double2 *Dc, const RingDesc &d,
+template <int NT, int MAXN, bool REG>
+__device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, double2 *Dc, int dc_cap, const RingTables &rt, const RingDesc &d,
                            const double2 *__restrict__ pool, const double2 *__restrict__ drow,
                            const int *__restrict__ minv, int mcontig, int mmax,
                            double *__restrict__ out)
 {
+    Chirps<NT, MAXN, REG> ch;
+    ring_tables_load<NT, MAXN, REG>(rt, d, pool, ch);
     const int n = d.n;
     const bool even = (n % 2) == 0;
     const int h = n / 2;
@@ -325,9 +420,9 @@ __device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, d
         // m = j n - k directly.  With w = e^{i n phi0},
         //   F_k = e^{i k phi0} (sum_j Delta_{k+jn} w^j + sum_{j>=1} conj(Delta_{jn-k}) conj(w^j)).
         // Few bins (small rings): G threads share a bin, each taking every
-        // G-th alias, and the G partial sums are added through LDS.
+        // G-th alias, and the G partial sums (G B <= dc_cap) are added through LDS.
         const int B = kmax + 1;
-        const int G = (B < NT) ? NT / B : 1;
+        const int G = (B < dc_cap) ? dc_cap / B : 1;
         const int kk = (G > 1) ? tid % B : tid;
         const int g = (G > 1) ? tid / B : 0;
         double2 stepG;   // w^G
@@ -388,19 +483,18 @@ __device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, d
     }
     __syncthreads();
     if (even) {
-        const double2 *tw = pool + d.tw;
         for (int k = tid; k <= h / 2; k += NT) {
             const int k2 = h - k;
             const double2 Fk = buf[k], Fk2 = buf[k2];
             const double2 e1 = cadd(Fk, conjd(Fk2)), o1 = csub(Fk, conjd(Fk2));
-            const double2 Zk = cadd(e1, muli(cmul(tw[k], o1), +1));
+            const double2 Zk = cadd(e1, muli(cmul(tw_at(rt.TW, k), o1), +1));
             const double2 e2 = cadd(Fk2, conjd(Fk)), o2 = csub(Fk2, conjd(Fk));
-            const double2 Zk2 = cadd(e2, muli(cmul(tw[k2], o2), +1));
+            const double2 Zk2 = cadd(e2, muli(cmul(tw_at(rt.TW, k2), o2), +1));
             buf[k] = Zk;
             if (k2 != k) buf[k2] = Zk2;
         }
         __syncthreads();
-        ring_dft<NT, MAXN>(buf, d, +1, pool);
+        ring_dft<NT, MAXN, REG>(buf, d, +1, pool, rt, ch);
         if ((reinterpret_cast<uintptr_t>(out) & 15) == 0) {
             double2 *o2 = reinterpret_cast<double2 *>(out);
             for (int j = tid; j < h; j += NT) o2[j] = buf[j];
@@ -412,7 +506,7 @@ __device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, d
             }
         }
     } else {
-        ring_dft<NT, MAXN>(buf, d, +1, pool);
+        ring_dft<NT, MAXN, REG>(buf, d, +1, pool, rt, ch);
         for (int j = tid; j < n; j += NT) out[j] = buf[j].x;
     }
 }
@@ -422,29 +516,35 @@ __global__ __launch_bounds__(NT, 4) void k_ring_synth(
     const int *__restrict__ ids, const RingDesc *__restrict__ rings,
     const double2 *__restrict__ pool, const double2 *__restrict__ delta,
     const int *__restrict__ minv, int mcontig, int mmax, int nm, int nrings,
-    double *__restrict__ map, long long npix, int dc_off)
+    double *__restrict__ map, long long npix, RingLds lds)
 {
     extern __shared__ double2 buf[];
     const int r = ids[xcd_logical(blockIdx.x, gridDim.x)];
     const long long b = blockIdx.y;
     const RingDesc d = rings[r];
-    synth_ring<NT, MAXN>(buf, buf + dc_off, d, pool, delta + (b * nrings + r) * nm, minv, mcontig,
-                         mmax, map + b * npix + d.start);
+    double2 *tw = buf + lds.fft_entries;
+    const RingTables rt = {tw, tw + lds.tw_entries};
+    synth_ring<NT, MAXN, true>(buf, tw + lds.tw_entries + lds.tb_entries, lds.dc_entries, rt, d,
+                               pool, delta + (b * nrings + r) * nm, minv, mcontig, mmax,
+                               map + b * npix + d.start);
 }
 
 // Batched synthesis: work item (map, ring) of a batch of plans.
 template <int NT, int MAXN>
 __global__ __launch_bounds__(NT, 4) void k_ring_synth_batch(
     const int2 *__restrict__ items, const BatchMap *__restrict__ maps,
-    double *const *__restrict__ outs, const char *__restrict__ ws, int dc_off)
+    double *const *__restrict__ outs, const char *__restrict__ ws, RingLds lds)
 {
     extern __shared__ double2 buf[];
     const int2 it = items[xcd_logical(blockIdx.x, gridDim.x)];
     const BatchMap &bm = maps[it.x];
     const RingDesc d = bm.rings[it.y];
     const double2 *delta = reinterpret_cast<const double2 *>(ws + bm.delta_off);
-    synth_ring<NT, MAXN>(buf, buf + dc_off, d, bm.pool, delta + (long long)it.y * bm.nm,
-                         bm.minv, bm.mcontig, bm.mmax, outs[it.x] + d.start);
+    double2 *tw = buf + lds.fft_entries;
+    const RingTables rt = {tw, tw + lds.tw_entries};
+    synth_ring<NT, MAXN, false>(buf, tw + lds.tw_entries + lds.tb_entries, lds.dc_entries, rt, d,
+                                bm.pool, delta + (long long)it.y * bm.nm, bm.minv, bm.mcontig,
+                                bm.mmax, outs[it.x] + d.start);
 }
 
 // Analysis (adjoint of the synthesis): G_k by a real DFT, then
@@ -453,12 +553,16 @@ template <int NT, int MAXN>
 __global__ __launch_bounds__(NT, 4) void k_ring_anal(
     const int *__restrict__ ids, const RingDesc *__restrict__ rings,
     const double2 *__restrict__ pool, const double *__restrict__ map, long long npix,
-    const int *__restrict__ mval, int mcontig, int nm, int nrings, double2 *__restrict__ dt)
+    const int *__restrict__ mval, int mcontig, int nm, int nrings, double2 *__restrict__ dt,
+    RingLds lds)
 {
     extern __shared__ double2 buf[];
     const int r = ids[xcd_logical(blockIdx.x, gridDim.x)];
     const int b = blockIdx.y;
     const RingDesc d = rings[r];
+    const RingTables rt = {buf + lds.fft_entries, buf + lds.fft_entries + lds.tw_entries};
+    Chirps<NT, MAXN, false> ch;
+    ring_tables_load<NT, MAXN, false>(rt, d, pool, ch);
     const double *in = map + (long long)b * npix + d.start;
     const int n = d.n;
     const bool even = (n % 2) == 0;
@@ -472,17 +576,16 @@ __global__ __launch_bounds__(NT, 4) void k_ring_anal(
             for (int j = tid; j < h; j += NT) buf[j] = make_double2(in[2 * j], in[2 * j + 1]);
         }
         __syncthreads();
-        ring_dft<NT, MAXN>(buf, d, -1, pool);
-        const double2 *tw = pool + d.tw;
+        ring_dft<NT, MAXN, false>(buf, d, -1, pool, rt, ch);
         for (int k = tid; k <= h / 2; k += NT) {
             const int k2 = h - k;
             const double2 Zk = buf[k];
             const double2 Zk2 = buf[k2 == h ? 0 : k2];
             // G_k = (Z_k + conj Z_{h-k})/2 - (i/2) e^{-2 pi i k/n} (Z_k - conj Z_{h-k})
             const double2 a1 = cadd(Zk, conjd(Zk2)), b1 = csub(Zk, conjd(Zk2));
-            const double2 G1 = csub(a1, muli(cmul(conjd(tw[k]), b1), +1));
+            const double2 G1 = csub(a1, muli(cmul(conjd(tw_at(rt.TW, k)), b1), +1));
             const double2 a2 = cadd(Zk2, conjd(Zk)), b2 = csub(Zk2, conjd(Zk));
-            const double2 G2 = csub(a2, muli(cmul(conjd(tw[k2]), b2), +1));
+            const double2 G2 = csub(a2, muli(cmul(conjd(tw_at(rt.TW, k2)), b2), +1));
             buf[k] = make_double2(0.5 * G1.x, 0.5 * G1.y);
             if (k2 != k) buf[k2] = make_double2(0.5 * G2.x, 0.5 * G2.y);
         }
@@ -490,7 +593,7 @@ __global__ __launch_bounds__(NT, 4) void k_ring_anal(
     } else {
         for (int j = tid; j < n; j += NT) buf[j] = make_double2(in[j], 0.0);
         __syncthreads();
-        ring_dft<NT, MAXN>(buf, d, -1, pool);
+        ring_dft<NT, MAXN, false>(buf, d, -1, pool, rt, ch);
     }
     const int kmax = even ? h : n - 1;
     double2 *orow = dt + ((long long)b * nrings + r) * nm;
@@ -539,8 +642,9 @@ __global__ __launch_bounds__(512) void k_bluestein_prep(
         else if (k > nb - len) m = nb - k;
         buf[k] = (m >= 0) ? conjd(chirp[m]) : make_double2(0.0, 0.0);
     }
+    load_tw<512>(buf + 8192, pool + d.twb, nb);
     __syncthreads();
-    fft_lds<512, 8192>(buf, nb, -1, pool + d.twb, 1);
+    fft_lds<512, 8192>(buf, nb, -1, buf + 8192, 1);
     const double inv = 1.0 / (double)nb;
     for (int k = threadIdx.x; k < nb; k += 512)
         pool[d.bq + k] = make_double2(buf[k].x * inv, buf[k].y * inv);
@@ -557,12 +661,12 @@ hipError_t synth_class(const sht_plan_s *p, int c, const double2 *delta, double 
 {
     const RingClass &rc = p->cls[c];
     if (rc.count == 0) return hipSuccess;
-    const size_t lds = (size_t)(rc.fft_entries + NT) * sizeof(double2);
+    const size_t lds = (size_t)rc.lds.total() * sizeof(double2);
     hipError_t e = set_lds((const void *)k_ring_synth<NT, MAXN>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_ring_synth<NT, MAXN>), dim3((unsigned)rc.count, (unsigned)p->nmaps),
                        dim3(NT), lds, st, rc.d_ids, p->d_rings, p->d_pool, delta, p->d_minv,
-                       p->mcontig, p->mmax, p->nm, p->nrings, map, p->npix, rc.fft_entries);
+                       p->mcontig, p->mmax, p->nm, p->nrings, map, p->npix, rc.lds);
     return hipGetLastError();
 }
 
@@ -571,18 +675,21 @@ hipError_t anal_class(const sht_plan_s *p, int c, const double *map, double2 *dt
 {
     const RingClass &rc = p->cls[c];
     if (rc.count == 0) return hipSuccess;
-    const size_t lds = (size_t)rc.fft_entries * sizeof(double2);
+    const size_t lds =
+        (size_t)(rc.lds.fft_entries + rc.lds.tw_entries + rc.lds.tb_entries) * sizeof(double2);
     hipError_t e = set_lds((const void *)k_ring_anal<NT, MAXN>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_ring_anal<NT, MAXN>), dim3((unsigned)rc.count, (unsigned)p->nmaps),
                        dim3(NT), lds, st, rc.d_ids, p->d_rings, p->d_pool, map, p->npix,
-                       p->d_mval, p->mcontig, p->nm, p->nrings, dt);
+                       p->d_mval, p->mcontig, p->nm, p->nrings, dt, rc.lds);
     return hipGetLastError();
 }
 
 }  // namespace
 
 // Size classes (FFT length limit): 0 -> 2048, 1 -> 4096, 2 -> 8192.
+static_assert(kClassThreads[0] == 256 && kClassThreads[1] == 512 && kClassThreads[2] == 1024,
+              "class thread counts must match the kernel instantiations");
 hipError_t launch_ring_synth(const sht_plan_s *p, const double2 *delta, double *map,
                              hipStream_t st)
 {
@@ -605,11 +712,11 @@ hipError_t synth_batch_class(const BatchClass &bc, const BatchMap *maps, double 
                              const void *ws, hipStream_t st)
 {
     if (bc.count == 0) return hipSuccess;
-    const size_t lds = (size_t)(bc.fft_entries + NT) * sizeof(double2);
+    const size_t lds = (size_t)bc.lds.total() * sizeof(double2);
     hipError_t e = set_lds((const void *)k_ring_synth_batch<NT, MAXN>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_ring_synth_batch<NT, MAXN>), dim3((unsigned)bc.count), dim3(NT), lds, st,
-                       bc.d_items, maps, outs, (const char *)ws, bc.fft_entries);
+                       bc.d_items, maps, outs, (const char *)ws, bc.lds);
     return hipGetLastError();
 }
 
@@ -626,7 +733,7 @@ hipError_t launch_bluestein_prep(const sht_plan_s *p, const int *ring_ids, int n
                                  hipStream_t st)
 {
     if (nids <= 0) return hipSuccess;
-    const size_t lds = (size_t)8192 * sizeof(double2);
+    const size_t lds = (size_t)(8192 + kTwEntries) * sizeof(double2);
     hipError_t e = set_lds((const void *)k_bluestein_prep, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bluestein_prep, dim3((unsigned)nids), dim3(512), lds, st,

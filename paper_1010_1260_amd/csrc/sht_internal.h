@@ -45,12 +45,44 @@ struct PairDesc {
 
 // Rings grouped by FFT length for the Fourier kernels (LDS and register
 // budgets differ per class): class 0 up to 2048 points, 1 up to 4096, 2 up to 8192.
+// LDS of a ring-class workgroup, in double2 entries: the spectrum / FFT
+// buffer, the two-level twiddle tables of the ring length (tw) and of the
+// Bluestein length (tb), and the staging of partial alias sums (dc, only
+// when some ring has fewer spectrum bins than threads).
+struct RingLds {
+    int fft_entries;
+    int tw_entries;
+    int tb_entries;
+    int dc_entries;
+    int total() const { return fft_entries + tw_entries + tb_entries + dc_entries; }
+};
+
 struct RingClass {
     int count;        // rings in the class
-    int fft_entries;  // LDS double2 entries of the spectrum / FFT buffer
+    RingLds lds;
     int *d_ids;       // device [count] ring indices
 };
 constexpr int kNumRingClasses = 3;
+constexpr int kClassThreads[kNumRingClasses] = {256, 512, 1024};
+
+// Grows a class layout by one ring of n pixels, Bluestein length nb (0 if
+// none) and spectrum / FFT need `need`.
+inline void ring_lds_add(RingLds &l, int c, int n, int nb, int need)
+{
+    const int nt = kClassThreads[c];
+    const int bins = (n % 2 == 0) ? n / 2 + 1 : n;
+    l.fft_entries = l.fft_entries > need ? l.fft_entries : need;
+    const int tw = 64 + (n + 63) / 64;
+    l.tw_entries = l.tw_entries > tw ? l.tw_entries : tw;
+    if (nb > 0) {
+        const int tb = 64 + (nb + 63) / 64;
+        l.tb_entries = l.tb_entries > tb ? l.tb_entries : tb;
+    }
+    if (bins < nt) {
+        const int dc = (c == 0) ? 128 : nt;
+        l.dc_entries = l.dc_entries > dc ? l.dc_entries : dc;
+    }
+}
 
 // One map of a batch of plans (device side): the plan's tables plus the
 // offsets of the map's buffers inside the batch workspace.
@@ -77,7 +109,7 @@ struct BatchTile {
 
 struct BatchClass {
     int count;        // (map, ring) items
-    int fft_entries;
+    RingLds lds;
     int2 *d_items;    // device [count] (map, ring)
 };
 
@@ -100,6 +132,8 @@ struct sht_plan_s {
     double *d_cn;        // [nalm] normalisation c_lm folded into the coefficients
     int32_t *d_minv;     // [mmax + 1] index of m in the set, -1 if absent
     long long *d_boff;   // [nm] first 32-step block of each m (split-BF16 operand packing)
+    long long *d_boff16; // [nm] first 16-row block of each m (FP32 matrix-core operand packing)
+    long long nblk16;    // 16-row blocks over all m
     sht::RingDesc *d_rings;
     double2 *d_pool;     // twiddle and Bluestein tables
     size_t table_bytes;
@@ -107,6 +141,8 @@ struct sht_plan_s {
     int mcontig;         // m-set is 0..nm-1
     std::vector<int> ring_class;  // size class of each ring's Fourier step
     std::vector<int> ring_need;   // LDS double2 entries of each ring's spectrum / FFT
+    std::vector<int> ring_n;      // pixels of each ring
+    std::vector<int> ring_nb;     // Bluestein length of each ring (0: none)
     sht::RingClass cls[sht::kNumRingClasses];
     size_t ws_ap_bytes;  // workspace: prescaled coefficients
     size_t ws_delta_bytes;

@@ -72,7 +72,7 @@ sht_status upload(T **dst, const std::vector<T> &src, size_t *acc)
 void free_tables(sht_plan_s *p)
 {
     void *ptrs[] = {p->d_pairs, p->d_mval, p->d_moff, p->d_mu, p->d_A, p->d_cn,
-                    p->d_minv, p->d_rings, p->d_pool, p->d_boff};
+                    p->d_minv, p->d_rings, p->d_pool, p->d_boff, p->d_boff16};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (int c = 0; c < sht::kNumRingClasses; ++c) {
@@ -81,7 +81,7 @@ void free_tables(sht_plan_s *p)
     }
     p->d_pairs = nullptr; p->d_mval = nullptr; p->d_moff = nullptr; p->d_mu = nullptr;
     p->d_A = nullptr; p->d_cn = nullptr; p->d_minv = nullptr; p->d_rings = nullptr;
-    p->d_pool = nullptr; p->d_boff = nullptr;
+    p->d_pool = nullptr; p->d_boff = nullptr; p->d_boff16 = nullptr;
 }
 
 sht_status check_plan(sht_plan_t p)
@@ -274,7 +274,7 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     // ---- Fourier classification per ring
     std::vector<RingDesc> rings(R);
     std::vector<int> ring_class(R);
-    int class_entries[sht::kNumRingClasses] = {0, 0, 0};
+    sht::RingLds class_lds[sht::kNumRingClasses] = {};
     for (int r = 0; r < R; ++r) {
         const long long n = d->nphi[r];
         RingDesc &g = rings[r];
@@ -297,7 +297,7 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
         const int need = std::max(spec, fftlen);
         const int c = fftlen <= 2048 ? 0 : (fftlen <= 4096 ? 1 : 2);
         ring_class[r] = c;
-        class_entries[c] = std::max(class_entries[c], need);
+        sht::ring_lds_add(class_lds[c], c, g.n, g.nb, need);
     }
 
     sht_plan_s *p = new (std::nothrow) sht_plan_s();
@@ -319,10 +319,14 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     p->nalm = p->moff.back();
     p->ring_class = ring_class;
     p->ring_need.resize(R);
+    p->ring_n.resize(R);
+    p->ring_nb.resize(R);
     for (int r = 0; r < R; ++r) {
         const RingDesc &g = rings[r];
         const int spec = (g.n % 2 == 0) ? g.clen + 1 : g.clen;
         p->ring_need[r] = std::max(spec, g.nb ? g.nb : g.clen);
+        p->ring_n[r] = g.n;
+        p->ring_nb[r] = g.nb;
     }
     p->mcontig = 1;
     for (int i = 0; i < d->nm; ++i)
@@ -396,6 +400,16 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
         }
         st = upload(&p->d_boff, boff, &tb);
     }
+    if (st == SHT_OK) {
+        std::vector<long long> boff16(d->nm);
+        long long acc_b = 0;
+        for (int i = 0; i < d->nm; ++i) {
+            boff16[i] = acc_b;
+            acc_b += (d->lmax - mval[i] + 1 + 15) / 16;
+        }
+        p->nblk16 = acc_b;
+        st = upload(&p->d_boff16, boff16, &tb);
+    }
     if (st == SHT_OK) st = upload(&p->d_rings, rings, &tb);
     if (st == SHT_OK) st = upload(&p->d_pool, pb.pool, &tb);
     for (int c = 0; c < sht::kNumRingClasses && st == SHT_OK; ++c) {
@@ -409,7 +423,7 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
             return d->nphi[a] > d->nphi[b];
         });
         p->cls[c].count = (int)ids.size();
-        p->cls[c].fft_entries = class_entries[c];
+        p->cls[c].lds = class_lds[c];
         st = upload(&p->cls[c].d_ids, ids, &tb);
     }
     if (st == SHT_OK && !prep_ids.empty()) {
