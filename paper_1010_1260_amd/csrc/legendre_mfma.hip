@@ -98,6 +98,7 @@ __global__ __launch_bounds__(256) void k_prescale_f32(
 // (addition theorem), so a wave whose lanes all reached k = 0 -- almost every
 // wave past its first l-steps -- needs neither the mask nor any rescaling.
 constexpr double kEmerge = 0x1p112;
+constexpr double kEmergeTrue = 0x1p-400;
 
 __device__ inline void rescale_mixed(double &ua, double &ub, int &k)
 {
@@ -159,14 +160,11 @@ __device__ __forceinline__ void block16(double x, double &ua, double &ub,
                                         const double2 *__restrict__ Ab,
                                         const v4f *__restrict__ Bb, bool live, MfmaTiles &acc)
 {
-    double2 a[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) a[t] = Ab[t];
     const v4f b03 = Bb[0], b47 = Bb[1];
     const float b[8] = {b03.x, b03.y, b03.z, b03.w, b47.x, b47.y, b47.z, b47.w};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const double2 a01 = a[2 * t], a23 = a[2 * t + 1];
+        const double2 a01 = Ab[2 * t], a23 = Ab[2 * t + 1];
         double u0, u1;
         if (SEED && t == 0) {
             u0 = ua;
@@ -185,6 +183,59 @@ __device__ __forceinline__ void block16(double x, double &ua, double &ub,
                   b[2 * t + 1], acc);
         else
             mfma4((float)u0, (float)u1, (float)u2, (float)u3, b[2 * t], b[2 * t + 1], acc);
+    }
+}
+
+// A block in which no lane of the wave has reached k = 0: every matrix
+// operand would be 0, so only the recurrence runs (same arithmetic, so the
+// state entering the next block is bitwise that of block16).
+template <bool SEED>
+__device__ __forceinline__ void block16_dead(double x, double &ua, double &ub,
+                                             const double2 *__restrict__ Ab)
+{
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const double2 a01 = Ab[2 * t], a23 = Ab[2 * t + 1];
+        double u0, u1;
+        if (SEED && t == 0) {
+            u0 = ua;
+            u1 = (a01.y * x) * ua;
+        } else {
+            u0 = fma(a01.x * x, ub, -ua);
+            u1 = fma(a01.y * x, u0, -ub);
+        }
+        const double u2 = fma(a23.x * x, u1, -u0);
+        const double u3 = fma(a23.y * x, u2, -u1);
+        ua = u2;
+        ub = u3;
+    }
+}
+
+// The same for a block read straight from the coefficient table, used while
+// the whole workgroup is still below 2^-400 (nothing staged in LDS).  The
+// block may run past the m's last row (the table is padded by 16 entries):
+// the state is then never used, since the m has no live rows left.
+template <bool SEED>
+__device__ __forceinline__ void block16_dead_g(double x, double &ua, double &ub,
+                                               const double *__restrict__ Am, int r0)
+{
+    double a[kBlk];
+#pragma unroll
+    for (int t = 0; t < kBlk; ++t) a[t] = Am[r0 + t];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        double u0, u1;
+        if (SEED && t == 0) {
+            u0 = ua;
+            u1 = (a[1] * x) * ua;
+        } else {
+            u0 = fma(a[4 * t] * x, ub, -ua);
+            u1 = fma(a[4 * t + 1] * x, u0, -ub);
+        }
+        const double u2 = fma(a[4 * t + 2] * x, u1, -u0);
+        const double u3 = fma(a[4 * t + 3] * x, u2, -u1);
+        ua = u2;
+        ub = u3;
     }
 }
 
@@ -234,79 +285,153 @@ __device__ __forceinline__ void super_compute(double x, double &ua, double &ub, 
     zero_tiles(acc);
     if (more) stage_load(g, Bm, nblk, Am, len, sb + 1, 0, tid);
     __builtin_amdgcn_sched_barrier(0);
-    if (seed)
-        block16<true, true>(x, ua, ub, As, Bs, k == 0, acc);
-    else
+    if (seed) {
+        if (wave_any(k == 0))
+            block16<true, true>(x, ua, ub, As, Bs, k == 0, acc);
+        else
+            block16_dead<true>(x, ua, ub, As);
+    } else if (!MASK || wave_any(k == 0)) {
         block16<MASK, false>(x, ua, ub, As, Bs, !MASK || k == 0, acc);
+    } else {
+        block16_dead<false>(x, ua, ub, As);
+    }
     if (MASK || seed) rescale_mixed(ua, ub, k);
     if (more) stage_store(g, nxt, 0, tid);
     for (int q = 1; q < nb; ++q) {
         if (more) stage_load(g, Bm, nblk, Am, len, sb + 1, q, tid);
         __builtin_amdgcn_sched_barrier(0);
-        block16<MASK, false>(x, ua, ub, As + (kBlk / 2) * q, Bs + (kBlkFloats / 4) * q,
-                             !MASK || k == 0, acc);
+        if (!MASK || wave_any(k == 0))
+            block16<MASK, false>(x, ua, ub, As + (kBlk / 2) * q, Bs + (kBlkFloats / 4) * q,
+                                 !MASK || k == 0, acc);
+        else
+            block16_dead<false>(x, ua, ub, As + (kBlk / 2) * q);
         if (MASK) rescale_mixed(ua, ub, k);
         if (more) stage_store(g, nxt, q, tid);
     }
     add_tiles(tot, acc);
 }
 
-// One m for the workgroup's 4 x 64 ring pairs.  Every thread runs the same
-// number of super-blocks and barriers.
-__device__ void mfma_one_m(char (*lds)[kBufBytes], double x, double s, int m, int i,
-                           long long off, long long boffi, double mum, int lmax,
-                           const double *__restrict__ A, const float *__restrict__ Bg,
-                           double *__restrict__ delta, const PairDesc *__restrict__ pairs,
-                           int npairs, int pb, int grp, int nmaps, int nrings, int nm)
+// A thread's share of a whole super-block copy (the first live one of an m):
+// 64 bytes of packed B and one dword of the coefficients.
+struct SuperStage {
+    v4f b[kSuper * kBlkFloats / 4 / kThreads];
+    unsigned a;
+};
+
+__device__ __forceinline__ void super_stage_load(SuperStage &g, const float *__restrict__ Bm,
+                                                 int nblk, const double *__restrict__ Am,
+                                                 int len, int sb, int tid)
 {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int hi = lane >> 5;
-    const int col = lane & 31;
-    const int len = lmax - m + 1;
-    const int nblk = (len + kBlk - 1) / kBlk;
-    const int nsb = (nblk + kSuper - 1) / kSuper;
-    const double *__restrict__ Am = A + off;
-    const float *__restrict__ Bm = Bg + boffi * kBlkFloats;
-
-    // first super-block: copied before the loop (a super-block with a
-    // successor always has kSuper blocks)
-    {
-        const int nb0 = min(kSuper, nblk);
-        for (int q = 0; q < nb0; ++q) {
-            Stage g;
-            stage_load(g, Bm, nblk, Am, len, 0, q, tid);
-            stage_store(g, lds[0], q, tid);
-        }
+    const int b0 = sb * kSuper;
+    const int nw = min(kSuper, nblk - b0) * (kBlkFloats / 4);  // 16-byte words present
+    const v4f *__restrict__ src = reinterpret_cast<const v4f *>(Bm + (long long)b0 * kBlkFloats);
+#pragma unroll
+    for (int c = 0; c < kSuper * kBlkFloats / 4 / kThreads; ++c) {
+        const int w = tid + kThreads * c;
+        g.b[c] = (w < nw) ? src[w] : v4f{};
     }
-    __syncthreads();
+    const int r = sb * kSuperRows + (tid >> 1);  // dword tid of the 128 coefficients
+    g.a = (r < len) ? reinterpret_cast<const unsigned *>(Am + r)[tid & 1] : 0u;
+}
 
-    double ua, ub = 0.0;
+__device__ __forceinline__ void super_stage_store(const SuperStage &g, char *buf, int tid)
+{
+    v4f *B = reinterpret_cast<v4f *>(buf + kABytes);
+#pragma unroll
+    for (int c = 0; c < kSuper * kBlkFloats / 4 / kThreads; ++c) B[tid + kThreads * c] = g.b[c];
+    reinterpret_cast<unsigned *>(buf)[tid] = g.a;
+}
+
+// One m of the workgroup's 4 x 64 ring pairs.
+struct MState {
+    int m, i, len, nblk, nsb, sb0;
+    const double *Am;
+    const float *Bm;
+    double ua, ub;
     int k;
-    seed_mm(mum, s, m, ua, k);
+};
 
-    MfmaTiles acc, tot;
+// Seed and phase 1: while no lane of the workgroup has reached k = 0, every
+// matrix operand is 0 (Q15), so the workgroup runs the recurrence alone, one
+// super-block at a time, with no staging.  Then the copy of the first live
+// super-block is issued into registers (committed to LDS by m_commit).
+__device__ void m_begin(MState &st, SuperStage &g, int i, const int *__restrict__ mval,
+                        const long long *__restrict__ moff, const long long *__restrict__ boff16,
+                        const double *__restrict__ mu, int lmax, const double *__restrict__ A,
+                        const float *__restrict__ Bg, double x, double s, int tid)
+{
+    st.i = i;
+    st.m = mval[i];
+    st.len = lmax - st.m + 1;
+    st.nblk = (st.len + kBlk - 1) / kBlk;
+    st.nsb = (st.nblk + kSuper - 1) / kSuper;
+    st.Am = A + moff[i];
+    st.Bm = Bg + boff16[i] * kBlkFloats;
+    st.ub = 0.0;
+    seed_mm(mu[i], s, st.m, st.ua, st.k);
+    // k = 0 only above 2^-400, also for the seed (kept exact: a power of two)
+    if (st.k == 0 && fabs(st.ua) < kEmergeTrue) {
+        st.ua *= kTwoS;
+        st.k = -1;
+    }
+    int sb0 = 0;
+    while (sb0 < st.nsb && !__syncthreads_or(st.k == 0)) {
+        const int nb = min(kSuper, st.nblk - sb0 * kSuper);
+        for (int q = 0; q < nb; ++q) {
+            const int r0 = (sb0 * kSuper + q) * kBlk;
+            if (r0 == 0)
+                block16_dead_g<true>(x, st.ua, st.ub, st.Am, r0);
+            else
+                block16_dead_g<false>(x, st.ua, st.ub, st.Am, r0);
+            rescale_mixed(st.ua, st.ub, st.k);
+        }
+        ++sb0;
+    }
+    st.sb0 = sb0;
+    if (sb0 < st.nsb) super_stage_load(g, st.Bm, st.nblk, st.Am, st.len, sb0, tid);
+}
+
+__device__ __forceinline__ void m_commit(const MState &st, const SuperStage &g,
+                                         char (*lds)[kBufBytes], int tid)
+{
+    if (st.sb0 < st.nsb) super_stage_store(g, lds[st.sb0 & 1], tid);
+    __syncthreads();
+}
+
+// Phase 2: the live super-blocks on the matrix cores; the second-level sums
+// end in tot.
+__device__ void m_compute(MState &st, char (*lds)[kBufBytes], double x, int tid, MfmaTiles &tot)
+{
+    MfmaTiles acc;
     zero_tiles(tot);
-    bool mask = true;  // the seed super-block runs masked
-    for (int sb = 0; sb < nsb; ++sb) {
-        const bool more = sb + 1 < nsb;
+    bool mask = true;  // the first live super-block runs masked
+    for (int sb = st.sb0; sb < st.nsb; ++sb) {
+        const bool more = sb + 1 < st.nsb;
         const char *cur = lds[sb & 1];
         char *nxt = lds[(sb + 1) & 1];
-        const int nb = min(kSuper, nblk - sb * kSuper);
+        const int nb = min(kSuper, st.nblk - sb * kSuper);
         if (mask) {
-            super_compute<true>(x, ua, ub, k, cur, nxt, more, sb, nb, sb == 0, Bm, nblk, Am, len,
-                                tid, acc, tot);
-            mask = wave_any(k < 0);
+            super_compute<true>(x, st.ua, st.ub, st.k, cur, nxt, more, sb, nb, sb == 0, st.Bm,
+                                st.nblk, st.Am, st.len, tid, acc, tot);
+            mask = wave_any(st.k < 0);
         } else {
-            super_compute<false>(x, ua, ub, k, cur, nxt, more, sb, nb, false, Bm, nblk, Am, len,
-                                 tid, acc, tot);
+            super_compute<false>(x, st.ua, st.ub, st.k, cur, nxt, more, sb, nb, false, st.Bm,
+                                 st.nblk, st.Am, st.len, tid, acc, tot);
         }
         __syncthreads();
     }
+}
 
-    // D layout of the 32x32 tile: column = lane % 32, row = 8 (r/4) + 4 (lane/32) + r % 4
+// Delta of one m: D layout of the 32x32 tile: column = lane % 32,
+// row = 8 (r/4) + 4 (lane/32) + r % 4.
+__device__ __forceinline__ void m_store(const MfmaTiles &tot, int i, double *__restrict__ delta,
+                                        const PairDesc *__restrict__ pairs, int npairs, int pb,
+                                        int grp, int nmaps, int nrings, int nm, int lane)
+{
+    const int hi = lane >> 5;
+    const int col = lane & 31;
     const int map = grp * 16 + (col >> 1);
-    if (map >= nmaps) return;  // no barrier follows in this m
+    if (map >= nmaps) return;
     const int part = col & 1;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -340,22 +465,34 @@ __global__ __launch_bounds__(kThreads, 2) void k_legendre_mfma_f32(
     const long long rest = L / pgroups;
     const int q = (int)(rest % nmpairs);
     const int grp = (int)(rest / nmpairs);
-    const int pb = pg * kWaves + (int)(threadIdx.x >> 6);
-    const int p = pb * 64 + (int)(threadIdx.x & 63);
+    const int tid = threadIdx.x;
+    const int pb = pg * kWaves + (tid >> 6);
+    const int p = pb * 64 + (tid & 63);
     double x = 0.0, s = 0.0;
     if (p < npairs) {
         const PairDesc d = pairs[p];
         x = d.x; s = d.s;
     }
     const float *Bg = Bp + (long long)grp * nblocks * kBlkFloats;
-    // the second m of the pair (if any) is taken by every thread of the
-    // workgroup, so the barrier count stays uniform; the last barrier of the
-    // first m orders its LDS reads before the second m's first copy
-    for (int t = 0; t < 2; ++t) {
-        const int i = (t == 0) ? q : nm - 1 - q;
-        if (t == 1 && i == q) break;
-        mfma_one_m(lds, x, s, mval[i], i, moff[i], boff16[i], mu[i], lmax, A, Bg, delta, pairs,
-                   npairs, pb, grp, nmaps, nrings, nm);
+    // Both m of the pair are run by every thread of the workgroup, so the
+    // barrier count stays uniform.  The second m's recurrence prefix and
+    // first copy are issued before the first m's Delta stores, so that its
+    // wait for the copy does not also wait for those stores.
+    MState st;
+    SuperStage g;
+    MfmaTiles tot;
+    m_begin(st, g, q, mval, moff, boff16, mu, lmax, A, Bg, x, s, tid);
+    m_commit(st, g, lds, tid);
+    m_compute(st, lds, x, tid, tot);
+    const int i1 = st.i;
+    const int i2 = nm - 1 - q;
+    const bool two = i2 != q;
+    if (two) m_begin(st, g, i2, mval, moff, boff16, mu, lmax, A, Bg, x, s, tid);
+    m_store(tot, i1, delta, pairs, npairs, pb, grp, nmaps, nrings, nm, tid & 63);
+    if (two) {
+        m_commit(st, g, lds, tid);
+        m_compute(st, lds, x, tid, tot);
+        m_store(tot, st.i, delta, pairs, npairs, pb, grp, nmaps, nrings, nm, tid & 63);
     }
 }
 
