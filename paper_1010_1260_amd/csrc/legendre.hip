@@ -14,14 +14,10 @@
 // exponent m/2 on 1-x^2) and P_{m+1,m} = sqrt(2m+3) x P_mm (Eq. pm1m).
 //
 // Rescaling (Sec. 2.2.2).  A lane carries (v, k) with value v 2^(512 k),
-// k <= 0.  Every 8 steps, if |v| > 2^512 (k <= -2) or |v| > 2^112 (k = -1),
-// both recurrence values and the accumulators are multiplied by 2^-512
-// (exact) and k grows by one; a seed below 2^-400 starts at k = -1.  So k = 0
-// exactly when the value has passed 2^-400, and k = 0 values never grow
-// past sqrt((2l+1)/4pi)/c_l (addition theorem).  The accumulators always hold
-// sum a' u 2^(512 (k_l - k)), and the result is acc * 2^(512 k): 1 for k = 0,
-// 2^-512 for k = -1, 0 below.  While no lane of the wave has reached k = 0,
-// the accumulation is skipped: the dropped terms are below 2^-330 a'.
+// k <= 0.  Every 8 steps, if |v| > 2^512, both recurrence values and the
+// accumulators are multiplied by 2^-512 (exact) and k grows by one.  The
+// accumulators therefore always hold sum a' u 2^(512 (k_l - k)), and the
+// result is acc * 2^(512 k): 1 for k = 0, 2^-512 for k = -1, 0 below.
 //
 // Mapping to CDNA4.  One wavefront owns 64*CH ring pairs (CH chains per
 // lane); the north/south rings of a pair share the recurrence through the
@@ -51,19 +47,6 @@ __global__ void k_prescale(const double2 *__restrict__ alm, const double *__rest
     ap[b * nalm + e] = a;
 }
 
-__device__ inline bool wave_any(bool c) { return __builtin_amdgcn_ballot_w64(c) != 0; }
-
-// k = 0 only above 2^-400, also for the seed (exact: a power of two)
-__device__ inline void seed_emerge(double &v, int &k)
-{
-    if (k == 0 && fabs(v) < 0x1p-400) {
-        v *= kTwoS;
-        k = -1;
-    }
-}
-
-__device__ inline double rescale_limit(int k) { return (k == -1) ? 0x1p112 : kTwoS; }
-
 template <int CH>
 struct Chains {
     double x[CH];
@@ -87,7 +70,6 @@ __device__ inline void fwd_one_m(const Chains<CH> &g, const double (&s)[CH], int
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             seed_mm(mum, s[c], m, u0[c], k[c]);
-            seed_emerge(u0[c], k[c]);
             Er[c] = a0.x * u0[c];
             Ei[c] = a0.y * u0[c];
             Or[c] = 0.0; Oi[c] = 0.0; u1[c] = 0.0;
@@ -103,53 +85,32 @@ __device__ inline void fwd_one_m(const Chains<CH> &g, const double (&s)[CH], int
             Oi[c] = a1.y * u1[c];
         }
     }
-    bool live = false;
-#pragma unroll
-    for (int c = 0; c < CH; ++c) live = live || (k[c] == 0);
-    live = wave_any(live);
     int j = 2;
     for (; j + 8 <= len; j += 8) {
-        if (live) {
 #pragma unroll
-            for (int t = 0; t < 8; t += 2) {
-                const double Aa = Am[j + t], Ab = Am[j + t + 1];
-                const double2 aa = am[j + t], ab = am[j + t + 1];
+        for (int t = 0; t < 8; t += 2) {
+            const double Aa = Am[j + t], Ab = Am[j + t + 1];
+            const double2 aa = am[j + t], ab = am[j + t + 1];
 #pragma unroll
-                for (int c = 0; c < CH; ++c) {
-                    const double u2 = fma(Aa * g.x[c], u1[c], -u0[c]);
-                    Er[c] = fma(aa.x, u2, Er[c]);
-                    Ei[c] = fma(aa.y, u2, Ei[c]);
-                    const double u3 = fma(Ab * g.x[c], u2, -u1[c]);
-                    Or[c] = fma(ab.x, u3, Or[c]);
-                    Oi[c] = fma(ab.y, u3, Oi[c]);
-                    u0[c] = u2; u1[c] = u3;
-                }
-            }
-        } else {
-            // every lane below 2^-400: recurrence only
-#pragma unroll
-            for (int t = 0; t < 8; t += 2) {
-                const double Aa = Am[j + t], Ab = Am[j + t + 1];
-#pragma unroll
-                for (int c = 0; c < CH; ++c) {
-                    const double u2 = fma(Aa * g.x[c], u1[c], -u0[c]);
-                    const double u3 = fma(Ab * g.x[c], u2, -u1[c]);
-                    u0[c] = u2; u1[c] = u3;
-                }
+            for (int c = 0; c < CH; ++c) {
+                const double u2 = fma(Aa * g.x[c], u1[c], -u0[c]);
+                Er[c] = fma(aa.x, u2, Er[c]);
+                Ei[c] = fma(aa.y, u2, Ei[c]);
+                const double u3 = fma(Ab * g.x[c], u2, -u1[c]);
+                Or[c] = fma(ab.x, u3, Or[c]);
+                Oi[c] = fma(ab.y, u3, Oi[c]);
+                u0[c] = u2; u1[c] = u3;
             }
         }
-        bool now = false;
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
-            if (k[c] < 0 && fmax(fabs(u0[c]), fabs(u1[c])) > rescale_limit(k[c])) {
+            if (fmax(fabs(u0[c]), fabs(u1[c])) > kTwoS) {
                 u0[c] *= kTwoMinusS; u1[c] *= kTwoMinusS;
                 Er[c] *= kTwoMinusS; Ei[c] *= kTwoMinusS;
                 Or[c] *= kTwoMinusS; Oi[c] *= kTwoMinusS;
                 k[c] += 1;
             }
-            now = now || (k[c] == 0);
         }
-        if (!live) live = wave_any(now);
     }
     for (; j < len; ++j) {
         const double Aa = Am[j];
