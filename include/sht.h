@@ -165,13 +165,15 @@ sht_status sht_alm2map_adjoint(sht_plan_t plan, const double *map, double *alm,
                                void *ws, size_t ws_bytes, void *stream);
 
 /* The two stages on their own (same kernels as sht_alm2map).
- * delta: device complex128 [nmaps][nrings][nm], Delta_m(theta_r) of
- * Eq. (DeltaDef) for the i-th m of the set at [b][r][i]. */
+ * delta: device complex128 [nmaps][nm][nrings], Delta_m(theta_r) of
+ * Eq. (DeltaDef) for the i-th m of the set at [b][i][r] (rings contiguous:
+ * the Legendre stage writes whole runs of rings per m). */
 sht_status sht_alm2delta(sht_plan_t plan, const double *alm, double *delta,
                          void *ws, size_t ws_bytes, void *stream);
 sht_status sht_delta2map(sht_plan_t plan, const double *delta, double *map, void *stream);
 
-/* Adjoint stages: map -> Delta~ (ring analysis) and Delta~ -> alm. */
+/* Adjoint stages: map -> Delta~ (ring analysis) and Delta~ -> alm; Delta~ has
+ * the layout of delta above. */
 sht_status sht_map2delta_adjoint(sht_plan_t plan, const double *map, double *delta,
                                  void *stream);
 sht_status sht_delta2alm_adjoint(sht_plan_t plan, const double *delta, double *alm,

@@ -58,7 +58,7 @@ template <int CH>
 __device__ inline void fwd_one_m(const Chains<CH> &g, const double (&s)[CH], int m, int i,
                                  long long off, double mum, int lmax,
                                  const double *__restrict__ A, const double2 *__restrict__ ap,
-                                 double2 *__restrict__ delta, long long dbase, int nm)
+                                 double2 *__restrict__ delta, long long dbase, int nrings)
 {
     const int len = lmax - m + 1;
     const double *__restrict__ Am = A + off;
@@ -136,11 +136,12 @@ __device__ inline void fwd_one_m(const Chains<CH> &g, const double (&s)[CH], int
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
         const double f = final_scale(k[c]);
+        // Delta [m][ring]: consecutive lanes write consecutive rings
         if (g.rn[c] >= 0)
-            delta[dbase + (long long)g.rn[c] * nm + i] =
+            delta[dbase + (long long)i * nrings + g.rn[c]] =
                 make_double2((Er[c] + Or[c]) * f, (Ei[c] + Oi[c]) * f);
         if (g.rs[c] >= 0)
-            delta[dbase + (long long)g.rs[c] * nm + i] =
+            delta[dbase + (long long)i * nrings + g.rs[c]] =
                 make_double2((Er[c] - Or[c]) * f, (Ei[c] - Oi[c]) * f);
     }
 }
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(64) void k_legendre_fwd(
     for (int t = 0; t < 2; ++t) {
         const int i = (t == 0) ? q : nm - 1 - q;
         if (t == 1 && i == q) break;
-        fwd_one_m<CH>(g, s, mval[i], i, moff[i], mu[i], lmax, A, apb, delta, dbase, nm);
+        fwd_one_m<CH>(g, s, mval[i], i, moff[i], mu[i], lmax, A, apb, delta, dbase, nrings);
     }
 }
 
@@ -196,7 +197,7 @@ template <int CH>
 __device__ inline void adj_one_m(const Chains<CH> &g, const double (&s)[CH], int m, int i,
                                  long long off, double mum, int lmax,
                                  const double *__restrict__ A,
-                                 const double2 *__restrict__ dt, long long dtbase, int nm,
+                                 const double2 *__restrict__ dt, long long dtbase, int nrings,
                                  double2 *__restrict__ part, double2 (*red)[64])
 {
     const int len = lmax - m + 1;
@@ -209,8 +210,8 @@ __device__ inline void adj_one_m(const Chains<CH> &g, const double (&s)[CH], int
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
         double2 wn = make_double2(0.0, 0.0), ws = make_double2(0.0, 0.0);
-        if (g.rn[c] >= 0) wn = dt[dtbase + (long long)g.rn[c] * nm + i];
-        if (g.rs[c] >= 0) ws = dt[dtbase + (long long)g.rs[c] * nm + i];
+        if (g.rn[c] >= 0) wn = dt[dtbase + (long long)i * nrings + g.rn[c]];
+        if (g.rs[c] >= 0) ws = dt[dtbase + (long long)i * nrings + g.rs[c]];
         NEr[c] = wn.x + ws.x; NEi[c] = wn.y + ws.y;
         NOr[c] = wn.x - ws.x; NOi[c] = wn.y - ws.y;
         seed_mm(mum, s[c], m, u0[c], k[c]);
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(64) void k_legendre_adj(
     for (int t = 0; t < 2; ++t) {
         const int i = (t == 0) ? q : nm - 1 - q;
         if (t == 1 && i == q) break;
-        adj_one_m<CH>(g, s, mval[i], i, moff[i], mu[i], lmax, A, dt, dtbase, nm, pp, red);
+        adj_one_m<CH>(g, s, mval[i], i, moff[i], mu[i], lmax, A, dt, dtbase, nrings, pp, red);
     }
 }
 
@@ -393,7 +394,7 @@ __global__ __launch_bounds__(64) void k_legendre_fwd_batch(const BatchTile *__re
             const int i = (u == 0) ? q : bm.nm - 1 - q;
             if (u == 1 && i == q) break;
             fwd_one_m<CH>(g, s, bm.mval[i], i, bm.moff[i], bm.mu[i], bm.lmax, bm.A, ap, delta, 0,
-                          bm.nm);
+                          bm.nrings);
         }
     }
 }

@@ -124,18 +124,18 @@ __device__ inline void parity_mfma(const float (&v)[16], const v8bf (&B)[3], v16
     swap8(Xh, Yh, A0h, A1h);
     swap8(Xm, Ym, A0m, A1m);
     swap8(Xl, Yl, A0l, A1l);
-    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0h, B[0], acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1h, B[0], acc1, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0h, B[1], acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1h, B[1], acc1, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0m, B[0], acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1m, B[0], acc1, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0h, B[2], acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1h, B[2], acc1, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0m, B[1], acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1m, B[1], acc1, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0l, B[0], acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1l, B[0], acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(B[0], A0h, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(B[0], A1h, acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(B[1], A0h, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(B[1], A1h, acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(B[0], A0m, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(B[0], A1m, acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(B[2], A0h, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(B[2], A1h, acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(B[1], A0m, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(B[1], A1m, acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(B[0], A0l, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(B[0], A1l, acc1, 0, 0, 0);
 }
 
 // tot[0..15] += e0, [16..31] += e1, [32..47] += o0, [48..63] += o1 (per lane)
@@ -228,22 +228,29 @@ __device__ void bf16_one_m(float *tot, double x, double s, int m, int i, long lo
     }
     flush_tot(acc, tot, lane);
 
-    const int map = grp * 16 + (col >> 1);
-    if (map >= nmaps) return;
-    const int part = col & 1;
+    // The tiles hold the transposed product (B operand first): column =
+    // lane % 32 is the ring pair, row = 8 (r/4) + 4 (lane/32) + r % 4 is
+    // (map, Re/Im), so each lane owns 8 complex values of one pair and a
+    // half-wave stores 32 consecutive rings of Delta [map][m][ring].
+    double2 *__restrict__ d2 = reinterpret_cast<double2 *>(delta);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
+        const int pp = pb * 64 + h * 32 + col;
+        if (pp < npairs) {
+            const PairDesc d = pairs[pp];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = 8 * (r >> 2) + 4 * hi + (r & 3);
-            const int pp = pb * 64 + h * 32 + row;
-            if (pp < npairs) {
-                const PairDesc d = pairs[pp];
-                const double ev = (double)tot[((h ? 16 : 0) + r) * 64 + lane];
-                const double ov = (double)tot[((h ? 48 : 32) + r) * 64 + lane];
-                delta[(((long long)map * nrings + d.rn) * nm + i) * 2 + part] = ev + ov;
-                if (d.rs >= 0)
-                    delta[(((long long)map * nrings + d.rs) * nm + i) * 2 + part] = ev - ov;
+            for (int r = 0; r < 16; r += 2) {
+                const int map = grp * 16 + 4 * (r >> 2) + 2 * hi + ((r & 3) >> 1);
+                if (map < nmaps) {
+                    const double er = tot[((h ? 16 : 0) + r) * 64 + lane];
+                    const double ei = tot[((h ? 16 : 0) + r + 1) * 64 + lane];
+                    const double orr = tot[((h ? 48 : 32) + r) * 64 + lane];
+                    const double oi = tot[((h ? 48 : 32) + r + 1) * 64 + lane];
+                    d2[((long long)map * nm + i) * nrings + d.rn] = make_double2(er + orr, ei + oi);
+                    if (d.rs >= 0)
+                        d2[((long long)map * nm + i) * nrings + d.rs] =
+                            make_double2(er - orr, ei - oi);
+                }
             }
         }
     }

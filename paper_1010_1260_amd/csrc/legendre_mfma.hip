@@ -17,6 +17,10 @@
 // steps give X0 = P_l, X1 = P_{l+1}, X2 = P_{l+2}, X3 = P_{l+3} per lane, and
 // one v_permlane32_swap of (X0, X2) yields the even-parity fragments of both
 // row halves ([X0_lo | X2_lo] and [X0_hi | X2_hi]); (X1, X3) gives the odd ones.
+// The fragment layouts of the two operands are mirror images, so passing the
+// B fragment first yields the transposed tile C^T = B^T Lambda^T: each lane
+// then owns one ring pair's values for 8 (map, Re/Im) pairs, and the Delta
+// stores of a half-wave cover 32 consecutive rings.
 //
 // Work split.  A workgroup of four waves takes 256 ring pairs and an m-pair
 // (m, mmax - m).  Per super-block of 128 l-rows the coefficients A_l (FP64)
@@ -145,10 +149,12 @@ __device__ __forceinline__ void mfma4(float X0, float X1, float X2, float X3, fl
     float A0E, A1E, A0O, A1O;
     swap_halves(X0, X2, A0E, A1E);
     swap_halves(X1, X3, A0O, A1O);
-    acc.e0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0E, BE, acc.e0, 0, 0, 0);
-    acc.e1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1E, BE, acc.e1, 0, 0, 0);
-    acc.o0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0O, BO, acc.o0, 0, 0, 0);
-    acc.o1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1O, BO, acc.o1, 0, 0, 0);
+    // B operand first: the tiles hold the transposed product, (map, Re/Im)
+    // rows by ring-pair columns (see m_store)
+    acc.e0 = __builtin_amdgcn_mfma_f32_32x32x2f32(BE, A0E, acc.e0, 0, 0, 0);
+    acc.e1 = __builtin_amdgcn_mfma_f32_32x32x2f32(BE, A1E, acc.e1, 0, 0, 0);
+    acc.o0 = __builtin_amdgcn_mfma_f32_32x32x2f32(BO, A0O, acc.o0, 0, 0, 0);
+    acc.o1 = __builtin_amdgcn_mfma_f32_32x32x2f32(BO, A1O, acc.o1, 0, 0, 0);
 }
 
 // One block of 16 l-rows from LDS: Ab = its 16 coefficients, Bb = the lane's
@@ -422,31 +428,34 @@ __device__ void m_compute(MState &st, char (*lds)[kBufBytes], double x, int tid,
     }
 }
 
-// Delta of one m: D layout of the 32x32 tile: column = lane % 32,
-// row = 8 (r/4) + 4 (lane/32) + r % 4.
+// Delta of one m.  D layout of a 32x32 tile: column = lane % 32 (the ring
+// pair), row = 8 (r/4) + 4 (lane/32) + r % 4 = 2 map + Re/Im, so a lane owns
+// 8 complex values of one pair and a half-wave stores 32 consecutive rings
+// of Delta [map][m][ring].
 __device__ __forceinline__ void m_store(const MfmaTiles &tot, int i, double *__restrict__ delta,
                                         const PairDesc *__restrict__ pairs, int npairs, int pb,
                                         int grp, int nmaps, int nrings, int nm, int lane)
 {
     const int hi = lane >> 5;
     const int col = lane & 31;
-    const int map = grp * 16 + (col >> 1);
-    if (map >= nmaps) return;
-    const int part = col & 1;
+    double2 *__restrict__ d2 = reinterpret_cast<double2 *>(delta);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const v16f &E = h ? tot.e1 : tot.e0;
         const v16f &O = h ? tot.o1 : tot.o0;
+        const int pp = pb * 64 + h * 32 + col;
+        if (pp < npairs) {
+            const PairDesc d = pairs[pp];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = 8 * (r >> 2) + 4 * hi + (r & 3);
-            const int pp = pb * 64 + h * 32 + row;
-            if (pp < npairs) {
-                const PairDesc d = pairs[pp];
-                const double e = (double)E[r], o = (double)O[r];
-                delta[(((long long)map * nrings + d.rn) * nm + i) * 2 + part] = e + o;
-                if (d.rs >= 0)
-                    delta[(((long long)map * nrings + d.rs) * nm + i) * 2 + part] = e - o;
+            for (int r = 0; r < 16; r += 2) {
+                const int map = grp * 16 + 4 * (r >> 2) + 2 * hi + ((r & 3) >> 1);
+                if (map < nmaps) {
+                    const double er = E[r], ei = E[r + 1], orr = O[r], oi = O[r + 1];
+                    d2[((long long)map * nm + i) * nrings + d.rn] = make_double2(er + orr, ei + oi);
+                    if (d.rs >= 0)
+                        d2[((long long)map * nm + i) * nrings + d.rs] =
+                            make_double2(er - orr, ei - oi);
+                }
             }
         }
     }

@@ -346,12 +346,13 @@ __device__ inline int xcd_logical(int b, int total)
     return x * q + (x < r ? x : r) + i;
 }
 
-// Delta_m for mode m of a ring's row (zero for m outside the set).
-__device__ inline double2 load_mode(const double2 *__restrict__ drow,
+// Delta_m for mode m of a ring (zero for m outside the set); Delta is laid
+// out [m][ring], so the ring's modes are `dstride` entries apart.
+__device__ inline double2 load_mode(const double2 *__restrict__ drow, long long dstride,
                                     const int *__restrict__ minv, int mcontig, int m)
 {
     const int i = mcontig ? m : minv[m];
-    return (i >= 0) ? drow[i] : make_double2(0.0, 0.0);
+    return (i >= 0) ? drow[(long long)i * dstride] : make_double2(0.0, 0.0);
 }
 
 // Synthesis: one workgroup per (ring of this size class, map).  LDS: the
@@ -361,7 +362,7 @@ __device__ inline double2 load_mode(const double2 *__restrict__ drow,
 template <int NT, int MAXN, bool REG>
 __device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, double2 *Dc, int dc_cap, const RingTables &rt, const RingDesc &d,
                            const double2 *__restrict__ pool, const double2 *__restrict__ drow,
-                           const int *__restrict__ minv, int mcontig, int mmax,
+                           long long dstride, const int *__restrict__ minv, int mcontig, int mmax,
                            double *__restrict__ out)
 {
     Chirps<NT, MAXN, REG> ch;
@@ -399,9 +400,9 @@ __device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, d
 #pragma unroll
             for (int q = 0; q < kBatch; ++q) {
                 const int k = k0 + q * NT + tid;
-                raw[q] = (k <= kdir) ? load_mode(drow, minv, mcontig, k) : make_double2(0.0, 0.0);
+                raw[q] = (k <= kdir) ? load_mode(drow, dstride, minv, mcontig, k) : make_double2(0.0, 0.0);
                 rawc[q] = (k >= 1 && k <= kmax && n - k <= mmax)
-                              ? load_mode(drow, minv, mcontig, n - k) : make_double2(0.0, 0.0);
+                              ? load_mode(drow, dstride, minv, mcontig, n - k) : make_double2(0.0, 0.0);
             }
 #pragma unroll
             for (int q = 0; q < kBatch; ++q) {
@@ -449,14 +450,14 @@ __device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, d
                 }
                 const int md = k + j * n;
                 if (md <= mmax) {
-                    double2 D = load_mode(drow, minv, mcontig, md);
+                    double2 D = load_mode(drow, dstride, minv, mcontig, md);
                     if (md == 0) D.y = 0.0;
                     const double2 v = cmul(D, wj);
                     sr += v.x; si += v.y;
                 }
                 const int mc = j * n - k;
                 if (j >= 1 && mc <= mmax) {
-                    const double2 D = load_mode(drow, minv, mcontig, mc);
+                    const double2 D = load_mode(drow, dstride, minv, mcontig, mc);
                     const double2 v = cmul(conjd(D), conjd(wj));
                     sr += v.x; si += v.y;
                 }
@@ -525,7 +526,7 @@ __global__ __launch_bounds__(NT, 4) void k_ring_synth(
     double2 *tw = buf + lds.fft_entries;
     const RingTables rt = {tw, tw + lds.tw_entries};
     synth_ring<NT, MAXN, true>(buf, tw + lds.tw_entries + lds.tb_entries, lds.dc_entries, rt, d,
-                               pool, delta + (b * nrings + r) * nm, minv, mcontig, mmax,
+                               pool, delta + b * nm * nrings + r, nrings, minv, mcontig, mmax,
                                map + b * npix + d.start);
 }
 
@@ -543,7 +544,7 @@ __global__ __launch_bounds__(NT, 4) void k_ring_synth_batch(
     double2 *tw = buf + lds.fft_entries;
     const RingTables rt = {tw, tw + lds.tw_entries};
     synth_ring<NT, MAXN, false>(buf, tw + lds.tw_entries + lds.tb_entries, lds.dc_entries, rt, d,
-                                bm.pool, delta + (long long)it.y * bm.nm, bm.minv, bm.mcontig,
+                                bm.pool, delta + it.y, bm.nrings, bm.minv, bm.mcontig,
                                 bm.mmax, outs[it.x] + d.start);
 }
 
@@ -596,7 +597,7 @@ __global__ __launch_bounds__(NT, 4) void k_ring_anal(
         ring_dft<NT, MAXN, false>(buf, d, -1, pool, rt, ch);
     }
     const int kmax = even ? h : n - 1;
-    double2 *orow = dt + ((long long)b * nrings + r) * nm;
+    double2 *orow = dt + (long long)b * nm * nrings + r;   // [m][ring]
     double2 step, ph;   // e^{-i NT phi0}, e^{-i m phi0} for this thread's mode
     {
         double sn, cs;
@@ -623,7 +624,7 @@ __global__ __launch_bounds__(NT, 4) void k_ring_anal(
             v = cmul(G, ph);
             v.x *= 2.0; v.y *= 2.0;
         }
-        orow[i] = v;
+        orow[(long long)i * nrings] = v;
     }
 }
 

@@ -98,7 +98,7 @@ struct BatchMap {
     const double2 *pool;
     long long nalm;
     long long ap_off;     // prescaled coefficients (double2 [nalm]) in the workspace
-    long long delta_off;  // Delta (double2 [nrings][nm]) in the workspace
+    long long delta_off;  // Delta (double2 [nm][nrings]) in the workspace
     int lmax, mmax, nm, nrings, npairs, mcontig, m0len, pad;
 };
 

@@ -150,7 +150,7 @@ class Plan:
 
     def alm2delta(self, alm: torch.Tensor) -> torch.Tensor:
         a = self._alm_in(alm)
-        out = torch.empty((self.nmaps, self.nrings, self.nm), dtype=torch.complex128,
+        out = torch.empty((self.nmaps, self.nm, self.nrings), dtype=torch.complex128,
                           device=self.device)
         ws = self.workspace()
         L.check(L.load().sht_alm2delta(self._h, _ptr(a), _ptr(out), _ptr(ws), ws.numel(),
@@ -159,9 +159,9 @@ class Plan:
         return out
 
     def delta2map(self, delta: torch.Tensor) -> torch.Tensor:
-        if delta.dtype != torch.complex128 or tuple(delta.shape) != (self.nmaps, self.nrings,
-                                                                     self.nm):
-            raise ValueError("delta must be complex128 (nmaps, nrings, nm)")
+        if delta.dtype != torch.complex128 or tuple(delta.shape) != (self.nmaps, self.nm,
+                                                                     self.nrings):
+            raise ValueError("delta must be complex128 (nmaps, nm, nrings)")
         dl = delta.contiguous()
         out = self._new_map()
         L.check(L.load().sht_delta2map(self._h, _ptr(dl), _ptr(out),
@@ -171,7 +171,7 @@ class Plan:
 
     def map2delta_adjoint(self, m: torch.Tensor) -> torch.Tensor:
         mm = self._map_in(m)
-        out = torch.empty((self.nmaps, self.nrings, self.nm), dtype=torch.complex128,
+        out = torch.empty((self.nmaps, self.nm, self.nrings), dtype=torch.complex128,
                           device=self.device)
         L.check(L.load().sht_map2delta_adjoint(self._h, _ptr(mm), _ptr(out),
                                                ctypes.c_void_p(_cur_stream(self.device))),
@@ -179,6 +179,9 @@ class Plan:
         return out
 
     def delta2alm_adjoint(self, delta: torch.Tensor) -> torch.Tensor:
+        if delta.dtype != torch.complex128 or tuple(delta.shape) != (self.nmaps, self.nm,
+                                                                     self.nrings):
+            raise ValueError("delta must be complex128 (nmaps, nm, nrings)")
         dl = delta.contiguous()
         out = torch.empty((self.nmaps, self.nalm), dtype=torch.complex128, device=self.device)
         ws = self.workspace()

@@ -50,7 +50,7 @@ def test_mixed_delta_and_map_parity(P, lmax, nside, nmaps, prec):
                      for i in range(nmaps)])
     plan = P.Plan(lmax, g, nmaps=nmaps, precision=prec)
     a = torch.from_numpy(alms).to(_dev())
-    d = plan.alm2delta(a).cpu().numpy()
+    d = np.swapaxes(plan.alm2delta(a).cpu().numpy(), 1, 2)   # -> [map][ring][m]
     mp = plan.alm2map(a).cpu().numpy()
     for i in range(nmaps):
         e = ref.delta(lmax, None, g.cth, g.sth, alms[i])
@@ -67,7 +67,7 @@ def test_mixed_partial_mset_ragged(P, prec):
     g = W.ecp_geometry(37, 21)
     alms = np.stack([W.random_alm(lmax, [302, i], mval=mval) for i in range(5)])
     plan = P.Plan(lmax, g, mval=mval, nmaps=5, precision=prec)
-    d = plan.alm2delta(torch.from_numpy(alms).to(_dev())).cpu().numpy()
+    d = np.swapaxes(plan.alm2delta(torch.from_numpy(alms).to(_dev())).cpu().numpy(), 1, 2)
     for i in range(5):
         e = ref.delta(lmax, mval, g.cth, g.sth, alms[i])
         assert _rel(d[i], e) < TOL

@@ -51,7 +51,7 @@ def test_delta_parity_healpix(P, lmax, nside):
     g = W.healpix_geometry(nside)
     a = W.random_alm(lmax, [101, lmax])
     plan = P.Plan(lmax, g)
-    d = plan.alm2delta(_to_dev(a).reshape(1, -1)).cpu().numpy()[0]
+    d = plan.alm2delta(_to_dev(a).reshape(1, -1)).cpu().numpy()[0].T   # -> [ring][m]
     e = ref.delta(lmax, None, g.cth, g.sth, a)
     assert _rel(d, e) < 1e-12
     assert np.max(np.abs(d - e)) < 1e-12 * np.max(np.abs(e))
@@ -76,7 +76,7 @@ def test_delta_partial_mset_ragged_and_batch(P):
     g = W.ecp_geometry(37, 21)          # odd ring count, rings not multiple of 64
     alms = [W.random_alm(lmax, [103, i], mval=mval) for i in range(3)]
     plan = P.Plan(lmax, g, mval=mval, nmaps=3)
-    d = plan.alm2delta(_to_dev(np.stack(alms))).cpu().numpy()
+    d = np.swapaxes(plan.alm2delta(_to_dev(np.stack(alms))).cpu().numpy(), 1, 2)
     for i in range(3):
         e = ref.delta(lmax, mval, g.cth, g.sth, alms[i])
         assert _rel(d[i], e) < 1e-12
@@ -87,7 +87,7 @@ def test_delta_edge_cases(P):
     # lmax = 0
     g = W.healpix_geometry(2)
     a = np.array([0.7 + 0.3j])
-    d = P.Plan(0, g).alm2delta(_to_dev(a).reshape(1, -1)).cpu().numpy()[0]
+    d = P.Plan(0, g).alm2delta(_to_dev(a).reshape(1, -1)).cpu().numpy()[0].T
     assert np.allclose(d[:, 0], 0.7 / np.sqrt(4 * np.pi), rtol=1e-15, atol=0)
     # single m = lmax, and rings at the poles (s = 0) and equator
     geo = W.Geometry(np.array([1.0, 0.6, 0.0, -0.6, -1.0]), np.array([0.0, 0.8, 1.0, 0.8, 0.0]),
@@ -97,7 +97,7 @@ def test_delta_edge_cases(P):
                        (1, None)]:
         al = W.random_alm(lmax, [104, lmax], mval=mval, spectrum="flat")
         plan = P.Plan(lmax, geo, mval=mval)
-        d = plan.alm2delta(_to_dev(al).reshape(1, -1)).cpu().numpy()[0]
+        d = plan.alm2delta(_to_dev(al).reshape(1, -1)).cpu().numpy()[0].T
         e = ref.delta(lmax, mval, geo.cth, geo.sth, al)
         assert np.max(np.abs(d - e)) <= 1e-13 * max(1.0, np.max(np.abs(e)))
 
@@ -109,7 +109,7 @@ def test_delta_deep_rescaling(P):
     x, s = np.cos(th), np.sin(th)
     geo = W.Geometry(x, s, np.zeros(4), np.full(4, 8, np.int64), np.arange(4) * 8, 32)
     a = W.random_alm(lmax, [105], spectrum="flat")
-    d = P.Plan(lmax, geo).alm2delta(_to_dev(a).reshape(1, -1)).cpu().numpy()[0]
+    d = P.Plan(lmax, geo).alm2delta(_to_dev(a).reshape(1, -1)).cpu().numpy()[0].T
     e = ref.delta(lmax, None, x, s, a)
     for r in range(4):
         assert _rel(d[r], e[r]) < 1e-11, r
@@ -132,7 +132,7 @@ def test_ring_synthesis_parity(P, nphi):
     dl = rng.standard_normal((nr, mmax + 1)) + 1j * rng.standard_normal((nr, mmax + 1))
     dl[:, 0] = dl[:, 0].real
     plan = P.Plan(mmax, geo, mval=mval)
-    got = plan.delta2map(_to_dev(dl).reshape(1, nr, mmax + 1)).cpu().numpy()[0]
+    got = plan.delta2map(_to_dev(np.ascontiguousarray(dl.T)).reshape(1, mmax + 1, nr)).cpu().numpy()[0]
     exp = ref.map_from_delta(mval, geo, dl)
     assert np.max(np.abs(got - exp)) < 1e-13 * np.max(np.abs(exp)) * max(1, np.log2(nphi + 1))
 
@@ -149,7 +149,7 @@ def test_ring_analysis_parity(P, nphi):
                      np.full(nr, nphi, np.int64), np.arange(nr) * nphi, nr * nphi)
     g = rng.standard_normal(nr * nphi)
     plan = P.Plan(mmax, geo, mval=mval)
-    got = plan.map2delta_adjoint(_to_dev(g).reshape(1, -1)).cpu().numpy()[0]
+    got = plan.map2delta_adjoint(_to_dev(g).reshape(1, -1)).cpu().numpy()[0].T   # -> [ring][m]
     for r in range(nr):
         exp = ref.ring_analysis(g[r * nphi:(r + 1) * nphi], mval, phi0[r])
         assert np.max(np.abs(got[r] - exp)) < 1e-13 * np.max(np.abs(exp)) * max(1, np.log2(nphi + 1))
