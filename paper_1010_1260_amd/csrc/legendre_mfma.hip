@@ -245,52 +245,42 @@ __device__ __forceinline__ void block16_dead_g(double x, double &ua, double &ub,
     }
 }
 
-// A thread's share of one block of the next super-block in flight
-// (global -> registers -> LDS): 8 bytes of packed B, and for threads 0-7 two
-// coefficients.
-struct Stage {
-    float2 b;
-    double2 a;
-};
-
-__device__ __forceinline__ void stage_load(Stage &g, const float *__restrict__ Bm, int nblk,
-                                           const double *__restrict__ Am, int len, int sb, int q,
-                                           int tid)
+// Copy of super-block sb of an m (its 8 packed B blocks and 128
+// coefficients) into LDS buffer `buf`, straight from global memory to LDS
+// (no registers); it completes at the workgroup's next barrier.  Every lane
+// takes part (the LDS slot of a lane follows its position in the wave): past
+// the m's last block or row the copy reads neighbouring data or the padding
+// after the tables (128 coefficients, one super-block of B), which only
+// lands in rows that are never used or are multiplied by B = 0.
+__device__ __forceinline__ void super_dma(char *buf, const float *__restrict__ Bm,
+                                          const double *__restrict__ Am, int sb, int tid)
 {
-    const int blk = sb * kSuper + q;
-    g.b = (blk < nblk)
-              ? reinterpret_cast<const float2 *>(Bm + (long long)blk * kBlkFloats)[tid]
-              : make_float2(0.0f, 0.0f);
-    if (tid < kBlk / 2) {
-        const int r = blk * kBlk + 2 * tid;
-        g.a.x = (r < len) ? Am[r] : 0.0;
-        g.a.y = (r + 1 < len) ? Am[r + 1] : 0.0;
+    const float *src = Bm + (long long)sb * kSuper * kBlkFloats;
+    float *dst = reinterpret_cast<float *>(buf + kABytes);
+#pragma unroll
+    for (int c = 0; c < kSuper * kBlkFloats / 4 / kThreads; ++c) {
+        const int w = tid + kThreads * c;
+        __builtin_amdgcn_global_load_lds(src + 4 * w, dst + 4 * w, 16, 0, 0);
     }
+    const unsigned *asrc = reinterpret_cast<const unsigned *>(Am + (long long)sb * kSuperRows);
+    __builtin_amdgcn_global_load_lds(asrc + tid, reinterpret_cast<unsigned *>(buf) + tid, 4, 0, 0);
 }
 
-__device__ __forceinline__ void stage_store(const Stage &g, char *buf, int q, int tid)
-{
-    reinterpret_cast<float2 *>(buf + kABytes + q * kBlkFloats * 4)[tid] = g.b;
-    if (tid < kBlk / 2) reinterpret_cast<double2 *>(buf)[q * (kBlk / 2) + tid] = g.a;
-}
-
-// The blocks of super-block sb, held in LDS buffer `cur`, while block q of
-// super-block sb + 1 is copied into `nxt` (when `more`); the first-level sums
-// start from zero and are added into tot at the end.
+// The blocks of super-block sb, held in LDS buffer `cur`, while super-block
+// sb + 1 is copied into `nxt` (when `more`); the first-level sums start from
+// zero and are added into tot at the end.
 template <bool MASK>
 __device__ __forceinline__ void super_compute(double x, double &ua, double &ub, int &k,
                                               const char *cur, char *nxt, bool more, int sb,
                                               int nb, bool seed, const float *__restrict__ Bm,
-                                              int nblk, const double *__restrict__ Am, int len,
-                                              int tid, MfmaTiles &acc, MfmaTiles &tot)
+                                              const double *__restrict__ Am, int tid,
+                                              MfmaTiles &acc, MfmaTiles &tot)
 {
     const int lane = tid & 63;
     const double2 *As = reinterpret_cast<const double2 *>(cur);
     const v4f *Bs = reinterpret_cast<const v4f *>(cur + kABytes) + lane * 2;
-    Stage g;
     zero_tiles(acc);
-    if (more) stage_load(g, Bm, nblk, Am, len, sb + 1, 0, tid);
-    __builtin_amdgcn_sched_barrier(0);
+    if (more) super_dma(nxt, Bm, Am, sb + 1, tid);
     if (seed) {
         if (wave_any(k == 0))
             block16<true, true>(x, ua, ub, As, Bs, k == 0, acc);
@@ -302,17 +292,13 @@ __device__ __forceinline__ void super_compute(double x, double &ua, double &ub, 
         block16_dead<false>(x, ua, ub, As);
     }
     if (MASK || seed) rescale_mixed(ua, ub, k);
-    if (more) stage_store(g, nxt, 0, tid);
     for (int q = 1; q < nb; ++q) {
-        if (more) stage_load(g, Bm, nblk, Am, len, sb + 1, q, tid);
-        __builtin_amdgcn_sched_barrier(0);
         if (!MASK || wave_any(k == 0))
             block16<MASK, false>(x, ua, ub, As + (kBlk / 2) * q, Bs + (kBlkFloats / 4) * q,
                                  !MASK || k == 0, acc);
         else
             block16_dead<false>(x, ua, ub, As + (kBlk / 2) * q);
         if (MASK) rescale_mixed(ua, ub, k);
-        if (more) stage_store(g, nxt, q, tid);
     }
     add_tiles(tot, acc);
 }
@@ -397,34 +383,44 @@ __device__ void m_begin(MState &st, SuperStage &g, int i, const int *__restrict_
     if (sb0 < st.nsb) super_stage_load(g, st.Bm, st.nblk, st.Am, st.len, sb0, tid);
 }
 
-__device__ __forceinline__ void m_commit(const MState &st, const SuperStage &g,
-                                         char (*lds)[kBufBytes], int tid)
+// The first live super-block goes to buffer A; the following ones alternate.
+__device__ __forceinline__ void m_commit(const MState &st, const SuperStage &g, char *ldsA,
+                                         int tid)
 {
-    if (st.sb0 < st.nsb) super_stage_store(g, lds[st.sb0 & 1], tid);
+    if (st.sb0 < st.nsb) super_stage_store(g, ldsA, tid);
+    __syncthreads();
+}
+
+// One super-block of phase 2 (then the barrier that also completes the copy
+// of the next one).
+__device__ __forceinline__ void m_step(MState &st, int sb, const char *cur, char *nxt, double x,
+                                       int tid, bool &mask, MfmaTiles &acc, MfmaTiles &tot)
+{
+    const bool more = sb + 1 < st.nsb;
+    const int nb = min(kSuper, st.nblk - sb * kSuper);
+    if (mask) {
+        super_compute<true>(x, st.ua, st.ub, st.k, cur, nxt, more, sb, nb, sb == 0, st.Bm,
+                            st.Am, tid, acc, tot);
+        mask = wave_any(st.k < 0);
+    } else {
+        super_compute<false>(x, st.ua, st.ub, st.k, cur, nxt, more, sb, nb, false, st.Bm,
+                             st.Am, tid, acc, tot);
+    }
     __syncthreads();
 }
 
 // Phase 2: the live super-blocks on the matrix cores; the second-level sums
-// end in tot.
-__device__ void m_compute(MState &st, char (*lds)[kBufBytes], double x, int tid, MfmaTiles &tot)
+// end in tot.  The two LDS buffers are distinct objects and the loop takes
+// them in a fixed order, so the compiler sees that the reads of one never
+// wait for the copy into the other.
+__device__ __forceinline__ void m_compute(MState &st, char *ldsA, char *ldsB, double x, int tid, MfmaTiles &tot)
 {
     MfmaTiles acc;
     zero_tiles(tot);
     bool mask = true;  // the first live super-block runs masked
-    for (int sb = st.sb0; sb < st.nsb; ++sb) {
-        const bool more = sb + 1 < st.nsb;
-        const char *cur = lds[sb & 1];
-        char *nxt = lds[(sb + 1) & 1];
-        const int nb = min(kSuper, st.nblk - sb * kSuper);
-        if (mask) {
-            super_compute<true>(x, st.ua, st.ub, st.k, cur, nxt, more, sb, nb, sb == 0, st.Bm,
-                                st.nblk, st.Am, st.len, tid, acc, tot);
-            mask = wave_any(st.k < 0);
-        } else {
-            super_compute<false>(x, st.ua, st.ub, st.k, cur, nxt, more, sb, nb, false, st.Bm,
-                                 st.nblk, st.Am, st.len, tid, acc, tot);
-        }
-        __syncthreads();
+    for (int sb = st.sb0; sb < st.nsb; sb += 2) {
+        m_step(st, sb, ldsA, ldsB, x, tid, mask, acc, tot);
+        if (sb + 1 < st.nsb) m_step(st, sb + 1, ldsB, ldsA, x, tid, mask, acc, tot);
     }
 }
 
@@ -468,7 +464,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_legendre_mfma_f32(
     int lmax, const double *__restrict__ A, const float *__restrict__ Bp, long long nblocks,
     double *__restrict__ delta, int nrings, int nmaps, long long total)
 {
-    __shared__ __attribute__((aligned(16))) char lds[2][kBufBytes];
+    __shared__ __attribute__((aligned(16))) char ldsA[kBufBytes];
+    __shared__ __attribute__((aligned(16))) char ldsB[kBufBytes];
     const long long L = xcd_logical(blockIdx.x, total);
     const int pg = (int)(L % pgroups);
     const long long rest = L / pgroups;
@@ -491,16 +488,16 @@ __global__ __launch_bounds__(kThreads, 2) void k_legendre_mfma_f32(
     SuperStage g;
     MfmaTiles tot;
     m_begin(st, g, q, mval, moff, boff16, mu, lmax, A, Bg, x, s, tid);
-    m_commit(st, g, lds, tid);
-    m_compute(st, lds, x, tid, tot);
+    m_commit(st, g, ldsA, tid);
+    m_compute(st, ldsA, ldsB, x, tid, tot);
     const int i1 = st.i;
     const int i2 = nm - 1 - q;
     const bool two = i2 != q;
     if (two) m_begin(st, g, i2, mval, moff, boff16, mu, lmax, A, Bg, x, s, tid);
     m_store(tot, i1, delta, pairs, npairs, pb, grp, nmaps, nrings, nm, tid & 63);
     if (two) {
-        m_commit(st, g, lds, tid);
-        m_compute(st, lds, x, tid, tot);
+        m_commit(st, g, ldsA, tid);
+        m_compute(st, ldsA, ldsB, x, tid, tot);
         m_store(tot, st.i, delta, pairs, npairs, pb, grp, nmaps, nrings, nm, tid & 63);
     }
 }
@@ -510,7 +507,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_legendre_mfma_f32(
 size_t mfma_bf_bytes(const sht_plan_s *p)
 {
     const size_t groups = (size_t)((p->nmaps + 15) / 16);
-    return groups * (size_t)p->nblk16 * kBlkFloats * sizeof(float);
+    // plus one super-block: the copies of an m's last super-block may read past it
+    return (groups * (size_t)p->nblk16 + kSuper) * kBlkFloats * sizeof(float);
 }
 
 hipError_t launch_prescale_f32(const sht_plan_s *p, const double *alm, float *Bp, hipStream_t st)

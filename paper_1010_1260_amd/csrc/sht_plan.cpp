@@ -388,9 +388,10 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     if (st == SHT_OK) st = upload(&p->d_mval, mval, &tb);
     if (st == SHT_OK) st = upload(&p->d_moff, p->moff, &tb);
     if (st == SHT_OK) st = upload(&p->d_mu, mu, &tb);
-    // 16 zero coefficients past the end: whole 16-row blocks may be read
-    // unguarded (the mixed kernel's recurrence-only phase)
-    A.resize(A.size() + 16, 0.0);
+    // 128 zero coefficients past the end: whole 16-row blocks and 128-row
+    // super-blocks may be read unguarded (the mixed kernel's recurrence-only
+    // phase and its copies to LDS)
+    A.resize(A.size() + 128, 0.0);
     if (st == SHT_OK) st = upload(&p->d_A, A, &tb);
     if (st == SHT_OK) st = upload(&p->d_cn, cn, &tb);
     if (st == SHT_OK) st = upload(&p->d_minv, minv, &tb);
