@@ -56,40 +56,66 @@ constexpr int kBufBytes = kABytes + kSuper * kBlkFloats * 4;
 // Packed B: slot s = 2t + p of lane (hi, col) in block b of an m holds row
 // 16 b + 4 t + 2 hi + p (p = 0: even slot, 1: odd slot) of column col, i.e.
 // a'_lm = c_lm a_lm of map col / 2 (Re for even col, Im for odd), zero past
-// the m's last row.  One workgroup per block (its m found once), two floats
-// per thread.
+// the m's last row.  One workgroup per kPreBlocks consecutive blocks: the
+// m of each block is found once, the a_lm are read in runs of 16 rows per
+// map (each complex value once), and the packed blocks are assembled in LDS
+// and written out contiguously.
+constexpr int kPreBlocks = 8;
+
 __global__ __launch_bounds__(256) void k_prescale_f32(
     const double2 *__restrict__ alm, const double *__restrict__ cn,
     const long long *__restrict__ moff, const int *__restrict__ mval,
     const long long *__restrict__ boff16, int nm, int lmax, long long nalm, long long nblocks,
     int nmaps, long long m0len, float *__restrict__ Bp)
 {
-    const long long blk = blockIdx.x;
+    __shared__ __attribute__((aligned(16))) float stage[kPreBlocks * kBlkFloats];
+    __shared__ int bm[kPreBlocks];
+    const long long blk0 = (long long)blockIdx.x * kPreBlocks;
+    const int nb = (int)min((long long)kPreBlocks, nblocks - blk0);
     const int grp = blockIdx.y;
-    int lo = 0, hh = nm - 1;
-    while (lo < hh) {
-        const int mid = (lo + hh + 1) >> 1;
-        if (boff16[mid] <= blk) lo = mid; else hh = mid - 1;
-    }
-    const int i = lo;
-    const int len = lmax - mval[i] + 1;
-    const long long row0 = (blk - boff16[i]) * kBlk;
-    float *__restrict__ out = Bp + ((long long)grp * nblocks + blk) * kBlkFloats;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int w = threadIdx.x + 256 * h;
-        const int lane = w >> 3, slot = w & 7;
-        const int hi = lane >> 5, col = lane & 31;
-        const long long row = row0 + 4 * (slot >> 1) + 2 * hi + (slot & 1);
-        const int map = grp * 16 + (col >> 1);
-        float v = 0.0f;
-        if (row < len && map < nmaps) {
-            const long long e = moff[i] + row;
-            const double2 a = alm[(long long)map * nalm + e];
-            const double c = cn[e];
-            v = (float)((col & 1) ? ((e < m0len) ? 0.0 : a.y * c) : a.x * c);
+    const int tid = threadIdx.x;
+    if (tid < nb) {
+        const long long blk = blk0 + tid;
+        int lo = 0, hh = nm - 1;
+        while (lo < hh) {
+            const int mid = (lo + hh + 1) >> 1;
+            if (boff16[mid] <= blk) lo = mid; else hh = mid - 1;
         }
-        out[w] = v;
+        bm[tid] = lo;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPreBlocks * 16 * 16 / 256; ++q) {
+        const int idx = tid + 256 * q;
+        const int b = idx >> 8, mp = (idx >> 4) & 15, rb = idx & 15;   // block, map, row
+        if (b < nb) {
+            const int i = bm[b];
+            const int len = lmax - mval[i] + 1;
+            const long long row = (blk0 + b - boff16[i]) * kBlk + rb;
+            const int map = grp * 16 + mp;
+            float vr = 0.0f, vi = 0.0f;
+            if (row < len && map < nmaps) {
+                const long long e = moff[i] + row;
+                const double2 a = alm[(long long)map * nalm + e];
+                const double c = cn[e];
+                vr = (float)(a.x * c);
+                vi = (float)((e < m0len) ? 0.0 : a.y * c);
+            }
+            // row rb = 4 t + 2 hi + p sits in slot 2 t + p of lane 32 hi + col
+            const int slot = 2 * (rb >> 2) + (rb & 1);
+            const int hi = (rb >> 1) & 1;
+            float *s = stage + b * kBlkFloats + (hi * 32 + 2 * mp) * 8 + slot;
+            s[0] = vr;
+            s[8] = vi;
+        }
+    }
+    __syncthreads();
+    const float4 *s4 = reinterpret_cast<const float4 *>(stage);
+    float4 *o4 = reinterpret_cast<float4 *>(Bp + ((long long)grp * nblocks + blk0) * kBlkFloats);
+#pragma unroll
+    for (int q = 0; q < kPreBlocks * kBlkFloats / 4 / 256; ++q) {
+        const int w = tid + 256 * q;
+        if (w < nb * (kBlkFloats / 4)) o4[w] = s4[w];
     }
 }
 
@@ -516,7 +542,7 @@ hipError_t launch_prescale_f32(const sht_plan_s *p, const double *alm, float *Bp
     const long long m0len = (p->mval[0] == 0) ? (p->lmax + 1) : 0;
     const int groups = (p->nmaps + 15) / 16;
     if (p->nblk16 <= 0 || p->nblk16 > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    dim3 grid((unsigned)p->nblk16, (unsigned)groups);
+    dim3 grid((unsigned)((p->nblk16 + kPreBlocks - 1) / kPreBlocks), (unsigned)groups);
     hipLaunchKernelGGL(k_prescale_f32, grid, dim3(256), 0, st,
                        reinterpret_cast<const double2 *>(alm), p->d_cn, p->d_moff, p->d_mval,
                        p->d_boff16, p->nm, p->lmax, p->nalm, p->nblk16, p->nmaps, m0len, Bp);
