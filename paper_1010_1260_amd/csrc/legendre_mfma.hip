@@ -56,40 +56,29 @@ constexpr int kBufBytes = kABytes + kSuper * kBlkFloats * 4;
 // Packed B: slot s = 2t + p of lane (hi, col) in block b of an m holds row
 // 16 b + 4 t + 2 hi + p (p = 0: even slot, 1: odd slot) of column col, i.e.
 // a'_lm = c_lm a_lm of map col / 2 (Re for even col, Im for odd), zero past
-// the m's last row.  One workgroup per kPreBlocks consecutive blocks: the
-// m of each block is found once, the a_lm are read in runs of 16 rows per
-// map (each complex value once), and the packed blocks are assembled in LDS
-// and written out contiguously.
+// the m's last row.  One workgroup per kPreBlocks consecutive blocks (bm16:
+// the m of each block): the a_lm are read in runs of 16 rows per map (each
+// complex value once), and the packed blocks are assembled in LDS and
+// written out contiguously.
 constexpr int kPreBlocks = 8;
 
 __global__ __launch_bounds__(256) void k_prescale_f32(
     const double2 *__restrict__ alm, const double *__restrict__ cn,
     const long long *__restrict__ moff, const int *__restrict__ mval,
-    const long long *__restrict__ boff16, int nm, int lmax, long long nalm, long long nblocks,
-    int nmaps, long long m0len, float *__restrict__ Bp)
+    const long long *__restrict__ boff16, const int *__restrict__ bm16, int lmax,
+    long long nalm, long long nblocks, int nmaps, long long m0len, float *__restrict__ Bp)
 {
     __shared__ __attribute__((aligned(16))) float stage[kPreBlocks * kBlkFloats];
-    __shared__ int bm[kPreBlocks];
     const long long blk0 = (long long)blockIdx.x * kPreBlocks;
     const int nb = (int)min((long long)kPreBlocks, nblocks - blk0);
     const int grp = blockIdx.y;
     const int tid = threadIdx.x;
-    if (tid < nb) {
-        const long long blk = blk0 + tid;
-        int lo = 0, hh = nm - 1;
-        while (lo < hh) {
-            const int mid = (lo + hh + 1) >> 1;
-            if (boff16[mid] <= blk) lo = mid; else hh = mid - 1;
-        }
-        bm[tid] = lo;
-    }
-    __syncthreads();
 #pragma unroll
     for (int q = 0; q < kPreBlocks * 16 * 16 / 256; ++q) {
         const int idx = tid + 256 * q;
         const int b = idx >> 8, mp = (idx >> 4) & 15, rb = idx & 15;   // block, map, row
         if (b < nb) {
-            const int i = bm[b];
+            const int i = bm16[blk0 + b];
             const int len = lmax - mval[i] + 1;
             const long long row = (blk0 + b - boff16[i]) * kBlk + rb;
             const int map = grp * 16 + mp;
@@ -545,7 +534,7 @@ hipError_t launch_prescale_f32(const sht_plan_s *p, const double *alm, float *Bp
     dim3 grid((unsigned)((p->nblk16 + kPreBlocks - 1) / kPreBlocks), (unsigned)groups);
     hipLaunchKernelGGL(k_prescale_f32, grid, dim3(256), 0, st,
                        reinterpret_cast<const double2 *>(alm), p->d_cn, p->d_moff, p->d_mval,
-                       p->d_boff16, p->nm, p->lmax, p->nalm, p->nblk16, p->nmaps, m0len, Bp);
+                       p->d_boff16, p->d_bm16, p->lmax, p->nalm, p->nblk16, p->nmaps, m0len, Bp);
     return hipGetLastError();
 }
 
