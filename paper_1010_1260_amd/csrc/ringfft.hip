@@ -322,8 +322,70 @@ __device__ __attribute__((always_inline)) inline void ring_tables_load(const Rin
     load_tw<NT>(rt.TW, pool + d.tw, d.n);
     if (d.nb != 0) {
         load_tw<NT>(rt.TB, pool + d.twb, d.nb);
-        load_chirps<NT, MAXN, REG>(ch, pool + d.tch, d.clen);
+        load_chirps<NT, MAXN, REG>(ch, pool + d.tch, d.half ? d.clen / 2 : d.clen);
     }
+}
+
+// DFT of even length clen = 2 len whose half length is not 7-smooth:
+// with E = DFT_len(x_{2j}) and O = DFT_len(x_{2j+1}) (Bluestein each, one
+// after the other in the same LDS buffer), X_j = E_j + w^j O_j and
+// X_{j+len} = E_j - w^j O_j, w = e^{sign 2 pi i / clen}.  The ring is even,
+// so TW holds the n-th roots with n = 2 clen: w^j = TW(2 j).
+template <int NT, int MAXN, bool REG>
+__device__ __attribute__((always_inline)) inline void split_bluestein(
+    double2 *buf, const RingDesc &d, int sign, const double2 *__restrict__ pool,
+    const RingTables &rt, const Chirps<NT, MAXN, REG> &ch)
+{
+    constexpr int QH = (MAXN / 2 + NT - 1) / NT;
+    const int len = d.clen / 2;
+    const int tid = threadIdx.x;
+    // keep and odd live in private memory (written once, read once per
+    // half), not in registers across the Bluestein transforms
+    double2 keep[QH], odd[QH];
+    int zq = 0;
+    asm volatile("" : "+s"(zq));
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+        const int j = tid + q * NT;
+        if (j < len) {
+            keep[q ^ zq] = buf[2 * j];
+            odd[q ^ zq] = buf[2 * j + 1];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+        const int j = tid + q * NT;
+        if (j < len) buf[j] = keep[q ^ zq];
+    }
+    __syncthreads();
+    bluestein_lds<NT, MAXN, REG>(buf, len, d.nb, sign, ch, rt.TB, pool + d.bq);
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+        const int j = tid + q * NT;
+        if (j < len) keep[q ^ zq] = buf[j];   // E_j
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+        const int j = tid + q * NT;
+        if (j < len) buf[j] = odd[q ^ zq];
+    }
+    __syncthreads();
+    bluestein_lds<NT, MAXN, REG>(buf, len, d.nb, sign, ch, rt.TB, pool + d.bq);
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+        const int j = tid + q * NT;
+        if (j < len) {
+            double2 w = tw_at(rt.TW, 2 * j);
+            if (sign < 0) w.y = -w.y;
+            const double2 t = cmul(w, buf[j]);
+            const double2 e = keep[q ^ zq];
+            buf[j] = cadd(e, t);
+            buf[j + len] = csub(e, t);
+        }
+    }
+    __syncthreads();
 }
 
 template <int NT, int MAXN, bool REG>
@@ -333,6 +395,8 @@ __device__ __attribute__((always_inline)) inline void ring_dft(double2 *buf, con
 {
     if (d.nb == 0) {
         fft_lds<NT, MAXN>(buf, d.clen, sign, rt.TW, (d.n % 2 == 0) ? 2 : 1);
+    } else if (d.half) {
+        split_bluestein<NT, MAXN, REG>(buf, d, sign, pool, rt, ch);
     } else {
         bluestein_lds<NT, MAXN, REG>(buf, d.clen, d.nb, sign, ch, rt.TB, pool + d.bq);
     }
@@ -635,7 +699,7 @@ __global__ __launch_bounds__(512) void k_bluestein_prep(
 {
     extern __shared__ double2 buf[];
     const RingDesc d = rings[ids[blockIdx.x]];
-    const int len = d.clen, nb = d.nb;
+    const int len = d.half ? d.clen / 2 : d.clen, nb = d.nb;
     const double2 *chirp = pool + d.tch;
     for (int k = threadIdx.x; k < nb; k += 512) {
         int m = -1;

@@ -30,8 +30,10 @@ struct RingDesc {
     double phi0;
     int n;            // pixels in the ring
     int clen;         // complex FFT length: n / 2 (n even) or n (n odd)
-    int nb;           // Bluestein convolution length (power of two), 0 if clen is 7-smooth
-    int pad;
+    int nb;           // Bluestein convolution length (7-smooth), 0 if clen is 7-smooth
+    int half;         // 1: the clen-point DFT is two Bluestein DFTs of length clen / 2
+                      // (even- and odd-indexed inputs) and one radix-2 step; the
+                      // chirp, nb and kernel spectrum are those of length clen / 2
 };
 
 // One recurrence unit: a ring, or a ring and its mirror (cos negated,

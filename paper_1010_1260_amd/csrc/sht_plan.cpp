@@ -289,6 +289,13 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
         if (smooth7(g.clen) && g.clen <= 8192) {
             g.nb = 0;
             fftlen = g.clen;
+        } else if (n % 2 == 0 && g.clen % 2 == 0) {
+            // split into the even- and odd-indexed halves: Bluestein of
+            // length clen / 2 needs a convolution of only clen - 1 points
+            g.half = 1;
+            g.nb = next_smooth7((long long)g.clen - 1);
+            if (g.nb > 8192) return SHT_ERR_UNSUPPORTED;
+            fftlen = g.nb;
         } else {
             g.nb = next_smooth7(2LL * g.clen - 1);
             if (g.nb > 8192) return SHT_ERR_UNSUPPORTED;
@@ -368,12 +375,13 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
         RingDesc &g = rings[r];
         g.tw = pb.roots(g.n);
         if (g.nb) {
-            g.tch = pb.chirp(g.clen);
+            const int blen = g.half ? g.clen / 2 : g.clen;   // Bluestein length
+            g.tch = pb.chirp(blen);
             g.twb = pb.roots(g.nb);
-            auto it = bq_of_len.find(g.clen);
+            auto it = bq_of_len.find(blen);
             if (it == bq_of_len.end()) {
                 g.bq = pb.reserve(g.nb);
-                bq_of_len[g.clen] = g.bq;
+                bq_of_len[blen] = g.bq;
                 prep_ids.push_back(r);
             } else {
                 g.bq = it->second;
