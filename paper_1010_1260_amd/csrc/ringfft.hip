@@ -424,7 +424,7 @@ __device__ inline double2 load_mode(const double2 *__restrict__ drow, long long 
 // (RingLds).
 // Synthesis of one ring: drow = its Delta_m row, out = its first pixel.
 template <int NT, int MAXN, bool REG>
-__device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, double2 *Dc, int dc_cap, const RingTables &rt, const RingDesc &d,
+__device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, const RingTables &rt, const RingDesc &d,
                            const double2 *__restrict__ pool, const double2 *__restrict__ drow,
                            long long dstride, const int *__restrict__ minv, int mcontig, int mmax,
                            double *__restrict__ out)
@@ -484,10 +484,20 @@ __device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, d
         // wrap-around (n <= mmax): bin k gathers its aliases m = k + j n and
         // m = j n - k directly.  With w = e^{i n phi0},
         //   F_k = e^{i k phi0} (sum_j Delta_{k+jn} w^j + sum_{j>=1} conj(Delta_{jn-k}) conj(w^j)).
-        // Few bins (small rings): G threads share a bin, each taking every
-        // G-th alias, and the G partial sums (G B <= dc_cap) are added through LDS.
+        // Few bins (small rings): G = NT / B threads share a bin, each taking
+        // every G-th alias, and the G partial sums are staged in the spectrum
+        // buffer itself (the class layout gives it at least NT entries when
+        // some ring has fewer bins than threads) and added in a fixed order.
+        // G depends on the ring and NT only, so every launch of the ring
+        // rounds alike.  The aliases are fetched two at a time.
         const int B = kmax + 1;
-        const int G = (B < dc_cap) ? dc_cap / B : 1;
+        const int G = (B < NT) ? NT / B : 1;
+        double2 step;    // e^{i NT phi0}
+        {
+            double sn, cs;
+            sincos((double)NT * d.phi0, &sn, &cs);
+            step = make_double2(cs, sn);
+        }
         const int kk = (G > 1) ? tid % B : tid;
         const int g = (G > 1) ? tid / B : 0;
         double2 stepG;   // w^G
@@ -502,33 +512,46 @@ __device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, d
             sincos((double)kk * d.phi0, &sn, &cs);
             phb = make_double2(cs, sn);
         }
+        constexpr int U = 2;
         for (int k = kk; k <= kmax && g < G; k += NT) {
+            const int jmax = (mmax + k) / n;   // last alias with j n - k <= mmax
             double sr = 0.0, si = 0.0;
             int c = 0;
             double2 wj = make_double2(1.0, 0.0);
-            for (int j = g; k + j * n <= mmax || (j >= 1 && j * n - k <= mmax); j += G, ++c) {
-                if ((c & 31) == 0) {   // re-seed w^j every 32 aliases
-                    double sn, cs;
-                    sincos((double)j * (double)n * d.phi0, &sn, &cs);
-                    wj = make_double2(cs, sn);
+            for (int j0 = g; j0 <= jmax; j0 += U * G) {
+                double2 Dd[U], Dm[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = j0 + u * G;
+                    const int md = k + j * n, mc = j * n - k;
+                    Dd[u] = make_double2(0.0, 0.0);
+                    Dm[u] = make_double2(0.0, 0.0);
+                    if (j <= jmax) {
+                        if (md <= mmax) Dd[u] = load_mode(drow, dstride, minv, mcontig, md);
+                        if (j >= 1) Dm[u] = load_mode(drow, dstride, minv, mcontig, mc);
+                    }
+                    if (md == 0) Dd[u].y = 0.0;
                 }
-                const int md = k + j * n;
-                if (md <= mmax) {
-                    double2 D = load_mode(drow, dstride, minv, mcontig, md);
-                    if (md == 0) D.y = 0.0;
-                    const double2 v = cmul(D, wj);
-                    sr += v.x; si += v.y;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = j0 + u * G;
+                    if (j <= jmax) {
+                        if ((c & 31) == 0) {   // re-seed w^j every 32 aliases
+                            double sn, cs;
+                            sincos((double)j * (double)n * d.phi0, &sn, &cs);
+                            wj = make_double2(cs, sn);
+                        }
+                        const double2 v = cmul(Dd[u], wj);
+                        sr += v.x; si += v.y;
+                        const double2 vm = cmul(conjd(Dm[u]), conjd(wj));
+                        sr += vm.x; si += vm.y;
+                        wj = cmul(wj, stepG);
+                        ++c;
+                    }
                 }
-                const int mc = j * n - k;
-                if (j >= 1 && mc <= mmax) {
-                    const double2 D = load_mode(drow, dstride, minv, mcontig, mc);
-                    const double2 v = cmul(conjd(D), conjd(wj));
-                    sr += v.x; si += v.y;
-                }
-                wj = cmul(wj, stepG);
             }
             if (G > 1) {
-                Dc[g * B + k] = make_double2(sr, si);
+                buf[g * B + k] = make_double2(sr, si);
             } else {
                 buf[k] = cmul(phb, make_double2(sr, si));
                 phb = cmul(phb, step);
@@ -536,10 +559,12 @@ __device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, d
         }
         if (G > 1) {
             __syncthreads();
+            // column k of the staged partials is read and then overwritten
+            // (entry 0) by thread k alone
             if (tid < B) {
                 double sr = 0.0, si = 0.0;
                 for (int q = 0; q < G; ++q) {
-                    const double2 v = Dc[q * B + tid];
+                    const double2 v = buf[q * B + tid];
                     sr += v.x; si += v.y;
                 }
                 buf[tid] = cmul(phb, make_double2(sr, si));
@@ -589,7 +614,7 @@ __global__ __launch_bounds__(NT, 4) void k_ring_synth(
     const RingDesc d = rings[r];
     double2 *tw = buf + lds.fft_entries;
     const RingTables rt = {tw, tw + lds.tw_entries};
-    synth_ring<NT, MAXN, true>(buf, tw + lds.tw_entries + lds.tb_entries, lds.dc_entries, rt, d,
+    synth_ring<NT, MAXN, true>(buf, rt, d,
                                pool, delta + b * nm * nrings + r, nrings, minv, mcontig, mmax,
                                map + b * npix + d.start);
 }
@@ -607,7 +632,7 @@ __global__ __launch_bounds__(NT, 4) void k_ring_synth_batch(
     const double2 *delta = reinterpret_cast<const double2 *>(ws + bm.delta_off);
     double2 *tw = buf + lds.fft_entries;
     const RingTables rt = {tw, tw + lds.tw_entries};
-    synth_ring<NT, MAXN, false>(buf, tw + lds.tw_entries + lds.tb_entries, lds.dc_entries, rt, d,
+    synth_ring<NT, MAXN, false>(buf, rt, d,
                                 bm.pool, delta + it.y, bm.nrings, bm.minv, bm.mcontig,
                                 bm.mmax, outs[it.x] + d.start);
 }

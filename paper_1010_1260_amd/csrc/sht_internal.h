@@ -48,15 +48,14 @@ struct PairDesc {
 // Rings grouped by FFT length for the Fourier kernels (LDS and register
 // budgets differ per class): class 0 up to 2048 points, 1 up to 4096, 2 up to 8192.
 // LDS of a ring-class workgroup, in double2 entries: the spectrum / FFT
-// buffer, the two-level twiddle tables of the ring length (tw) and of the
-// Bluestein length (tb), and the staging of partial alias sums (dc, only
-// when some ring has fewer spectrum bins than threads).
+// buffer (which also stages partial alias sums during the fold), and the
+// two-level twiddle tables of the ring length (tw) and of the Bluestein
+// length (tb).
 struct RingLds {
     int fft_entries;
     int tw_entries;
     int tb_entries;
-    int dc_entries;
-    int total() const { return fft_entries + tw_entries + tb_entries + dc_entries; }
+    int total() const { return fft_entries + tw_entries + tb_entries; }
 };
 
 struct RingClass {
@@ -67,22 +66,21 @@ struct RingClass {
 constexpr int kNumRingClasses = 3;
 constexpr int kClassThreads[kNumRingClasses] = {256, 512, 1024};
 
-// Grows a class layout by one ring of n pixels, Bluestein length nb (0 if
-// none) and spectrum / FFT need `need`.
+// Grows the layout of class c by one ring of n pixels, Bluestein length nb
+// (0 if none) and spectrum / FFT need `need`.  A ring with fewer spectrum
+// bins than threads stages its partial alias sums in the buffer, which then
+// holds at least one entry per thread.
 inline void ring_lds_add(RingLds &l, int c, int n, int nb, int need)
 {
     const int nt = kClassThreads[c];
     const int bins = (n % 2 == 0) ? n / 2 + 1 : n;
+    if (bins < nt && need < nt) need = nt;
     l.fft_entries = l.fft_entries > need ? l.fft_entries : need;
     const int tw = 64 + (n + 63) / 64;
     l.tw_entries = l.tw_entries > tw ? l.tw_entries : tw;
     if (nb > 0) {
         const int tb = 64 + (nb + 63) / 64;
         l.tb_entries = l.tb_entries > tb ? l.tb_entries : tb;
-    }
-    if (bins < nt) {
-        const int dc = (c == 0) ? 128 : nt;
-        l.dc_entries = l.dc_entries > dc ? l.dc_entries : dc;
     }
 }
 
