@@ -34,15 +34,10 @@
 // matrix core accumulates the 64 same-parity terms of a super-block from zero
 // and the block sums are added into a second FP32 accumulator (two-level
 // summation).  Emulated error of Delta at l_max = 4096: about 1.2e-7 relative.
-#include "recurrence.h"
-#include "sht_internal.h"
+#include "mixed_common.h"
 
 namespace sht {
 namespace {
-
-typedef float v16f __attribute__((ext_vector_type(16)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 
 constexpr int kWaves = 4;                   // waves (64 ring pairs each) sharing an m
 constexpr int kThreads = 64 * kWaves;
@@ -106,54 +101,6 @@ __global__ __launch_bounds__(256) void k_prescale_f32(
         const int w = tid + 256 * q;
         if (w < nb * (kBlkFloats / 4)) o4[w] = s4[w];
     }
-}
-
-// Lane state of the mixed kernels.  u = P_l / c_l is carried as v 2^(512 k),
-// k <= 0, as in the FP64 kernel, but a lane moves up to k = 0 as soon as its
-// true value passes 2^-400 (|v| > 2^112 at k = -1).  Checked every 16 steps
-// (growth below 2^140), every lane with k < 0 then holds a true value below
-// 2^-260, which is zero in FP32: the matrix operand is (float)v for k = 0 and
-// 0 otherwise.  Values at k = 0 are bounded by sqrt((2l+1)/4pi)/c_l < 2^9
-// (addition theorem), so a wave whose lanes all reached k = 0 -- almost every
-// wave past its first l-steps -- needs neither the mask nor any rescaling.
-constexpr double kEmerge = 0x1p112;
-constexpr double kEmergeTrue = 0x1p-400;
-
-__device__ inline void rescale_mixed(double &ua, double &ub, int &k)
-{
-    if (k < 0) {
-        const double lim = (k == -1) ? kEmerge : kTwoS;
-        if (fmax(fabs(ua), fabs(ub)) > lim) {
-            ua *= kTwoMinusS; ub *= kTwoMinusS;
-            k += 1;
-        }
-    }
-}
-
-__device__ inline bool wave_any(bool c) { return __builtin_amdgcn_ballot_w64(c) != 0; }
-
-__device__ inline float opnd(double u, bool live) { return live ? (float)u : 0.0f; }
-
-__device__ inline void swap_halves(float a, float b, float &lo, float &hi)
-{
-    const v2u r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b),
-                                                   false, false);
-    lo = __uint_as_float(r[0]);
-    hi = __uint_as_float(r[1]);
-}
-
-struct MfmaTiles {
-    v16f e0, e1, o0, o1;  // even / odd parity, rows 0-31 / 32-63
-};
-
-__device__ __forceinline__ void zero_tiles(MfmaTiles &t)
-{
-    t.e0 = v16f{}; t.e1 = v16f{}; t.o0 = v16f{}; t.o1 = v16f{};
-}
-
-__device__ __forceinline__ void add_tiles(MfmaTiles &tot, const MfmaTiles &acc)
-{
-    tot.e0 += acc.e0; tot.e1 += acc.e1; tot.o0 += acc.o0; tot.o1 += acc.o1;
 }
 
 // Four MFMAs of one group of 4 l-values: X0..X3 = P_l..P_{l+3} of the lane's
@@ -227,34 +174,6 @@ __device__ __forceinline__ void block16_dead(double x, double &ua, double &ub,
         }
         const double u2 = fma(a23.x * x, u1, -u0);
         const double u3 = fma(a23.y * x, u2, -u1);
-        ua = u2;
-        ub = u3;
-    }
-}
-
-// The same for a block read straight from the coefficient table, used while
-// the whole workgroup is still below 2^-400 (nothing staged in LDS).  The
-// block may run past the m's last row (the table is padded by 16 entries):
-// the state is then never used, since the m has no live rows left.
-template <bool SEED>
-__device__ __forceinline__ void block16_dead_g(double x, double &ua, double &ub,
-                                               const double *__restrict__ Am, int r0)
-{
-    double a[kBlk];
-#pragma unroll
-    for (int t = 0; t < kBlk; ++t) a[t] = Am[r0 + t];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        double u0, u1;
-        if (SEED && t == 0) {
-            u0 = ua;
-            u1 = (a[1] * x) * ua;
-        } else {
-            u0 = fma(a[4 * t] * x, ub, -ua);
-            u1 = fma(a[4 * t + 1] * x, u0, -ub);
-        }
-        const double u2 = fma(a[4 * t + 2] * x, u1, -u0);
-        const double u3 = fma(a[4 * t + 3] * x, u2, -u1);
         ua = u2;
         ub = u3;
     }
@@ -436,39 +355,6 @@ __device__ __forceinline__ void m_compute(MState &st, char *ldsA, char *ldsB, do
     for (int sb = st.sb0; sb < st.nsb; sb += 2) {
         m_step(st, sb, ldsA, ldsB, x, tid, mask, acc, tot);
         if (sb + 1 < st.nsb) m_step(st, sb + 1, ldsB, ldsA, x, tid, mask, acc, tot);
-    }
-}
-
-// Delta of one m.  D layout of a 32x32 tile: column = lane % 32 (the ring
-// pair), row = 8 (r/4) + 4 (lane/32) + r % 4 = 2 map + Re/Im, so a lane owns
-// 8 complex values of one pair and a half-wave stores 32 consecutive rings
-// of Delta [map][m][ring].
-__device__ __forceinline__ void m_store(const MfmaTiles &tot, int i, double *__restrict__ delta,
-                                        const PairDesc *__restrict__ pairs, int npairs, int pb,
-                                        int grp, int nmaps, int nrings, int nm, int lane)
-{
-    const int hi = lane >> 5;
-    const int col = lane & 31;
-    double2 *__restrict__ d2 = reinterpret_cast<double2 *>(delta);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const v16f &E = h ? tot.e1 : tot.e0;
-        const v16f &O = h ? tot.o1 : tot.o0;
-        const int pp = pb * 64 + h * 32 + col;
-        if (pp < npairs) {
-            const PairDesc d = pairs[pp];
-#pragma unroll
-            for (int r = 0; r < 16; r += 2) {
-                const int map = grp * 16 + 4 * (r >> 2) + 2 * hi + ((r & 3) >> 1);
-                if (map < nmaps) {
-                    const double er = E[r], ei = E[r + 1], orr = O[r], oi = O[r + 1];
-                    d2[((long long)map * nm + i) * nrings + d.rn] = make_double2(er + orr, ei + oi);
-                    if (d.rs >= 0)
-                        d2[((long long)map * nm + i) * nrings + d.rs] =
-                            make_double2(er - orr, ei - oi);
-                }
-            }
-        }
     }
 }
 
