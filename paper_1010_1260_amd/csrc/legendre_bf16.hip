@@ -55,49 +55,62 @@ __device__ inline void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l)
 }
 
 // a'_lm = c_lm a_lm of up to 16 maps, split and packed per 32-step block.
-__global__ void k_prescale_bf16x3(const double2 *__restrict__ alm, const double *__restrict__ cn,
-                                  const long long *__restrict__ moff,
-                                  const int *__restrict__ mval, const long long *__restrict__ boff,
-                                  int nm, int lmax, long long nalm, long long nblocks,
-                                  int nmaps, long long m0len, v4u *__restrict__ Bb)
+// One workgroup per kPreBlocks consecutive blocks (bm32: the m of each
+// block): the a_lm are read in runs of 32 rows per map (each complex value
+// once), split, placed into the packed blocks in LDS, and the blocks are
+// written out contiguously.
+constexpr int kPreBlocks = 4;
+
+__global__ __launch_bounds__(256) void k_prescale_bf16x3(
+    const double2 *__restrict__ alm, const double *__restrict__ cn,
+    const long long *__restrict__ moff, const int *__restrict__ mval,
+    const long long *__restrict__ boff, const int *__restrict__ bm32, int lmax, long long nalm,
+    long long nblocks, int nmaps, long long m0len, v4u *__restrict__ Bb)
 {
-    // one thread per (block, parity, half, column): writes 3 x 16 bytes
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ __attribute__((aligned(16))) __bf16 stage[kPreBlocks * kBlkElems * 8];
+    const long long blk0 = (long long)blockIdx.x * kPreBlocks;
+    const int nb = (int)min((long long)kPreBlocks, nblocks - blk0);
     const int grp = blockIdx.y;
-    if (t >= nblocks * 128) return;
-    const long long blk = t >> 7;
-    const int col = (int)(t & 31);
-    const int half = (int)((t >> 5) & 1);
-    const int par = (int)((t >> 6) & 1);
-    // find the m of this block (binary search over boff)
-    int lo = 0, hi = nm - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (boff[mid] <= blk) lo = mid; else hi = mid - 1;
-    }
-    const int i = lo;
-    const int len = lmax - mval[i] + 1;
-    const long long b = blk - boff[i];
-    const int map = grp * 16 + (col >> 1);
-    v8bf H, M, L;
+    const int tid = threadIdx.x;
 #pragma unroll
-    for (int jp = 0; jp < 8; ++jp) {
-        const long long j = 32 * b + 2 * (8 * half + jp) + par;
-        float x = 0.0f;
-        if (j < len && map < nmaps) {
-            const long long e = moff[i] + j;
-            const double2 a = alm[(long long)map * nalm + e];
-            const double c = cn[e];
-            x = (float)((col & 1) ? ((e < m0len) ? 0.0 : a.y * c) : a.x * c);
+    for (int q = 0; q < kPreBlocks * kBlkSteps * 16 / 256; ++q) {
+        const int idx = tid + 256 * q;
+        const int b = idx >> 9, mp = (idx >> 5) & 15, rb = idx & 31;   // block, map, row
+        if (b < nb) {
+            const int i = bm32[blk0 + b];
+            const int len = lmax - mval[i] + 1;
+            const long long row = (blk0 + b - boff[i]) * kBlkSteps + rb;
+            const int map = grp * 16 + mp;
+            float xr = 0.0f, xi = 0.0f;
+            if (row < len && map < nmaps) {
+                const long long e = moff[i] + row;
+                const double2 a = alm[(long long)map * nalm + e];
+                const double c = cn[e];
+                xr = (float)(a.x * c);
+                xi = (float)((e < m0len) ? 0.0 : a.y * c);
+            }
+            // row rb = 2 K + parity; K = 8 half + slot
+            const int par = rb & 1, kk = rb >> 1, half = kk >> 3, slot = kk & 7;
+            __bf16 h, m, l;
+            __bf16 *s = stage + b * kBlkElems * 8;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                split3(c ? xi : xr, h, m, l);
+                const int col = 2 * mp + c;
+                s[(((par * 3 + 0) * 2 + half) * 32 + col) * 8 + slot] = h;
+                s[(((par * 3 + 1) * 2 + half) * 32 + col) * 8 + slot] = m;
+                s[(((par * 3 + 2) * 2 + half) * 32 + col) * 8 + slot] = l;
+            }
         }
-        __bf16 h, m, l;
-        split3(x, h, m, l);
-        H[jp] = h; M[jp] = m; L[jp] = l;
     }
-    v4u *dst = Bb + ((long long)grp * nblocks + blk) * kBlkElems;
-    dst[((par * 3 + 0) * 2 + half) * 32 + col] = __builtin_bit_cast(v4u, H);
-    dst[((par * 3 + 1) * 2 + half) * 32 + col] = __builtin_bit_cast(v4u, M);
-    dst[((par * 3 + 2) * 2 + half) * 32 + col] = __builtin_bit_cast(v4u, L);
+    __syncthreads();
+    const v4u *s4 = reinterpret_cast<const v4u *>(stage);
+    v4u *o4 = Bb + ((long long)grp * nblocks + blk0) * kBlkElems;
+#pragma unroll
+    for (int q = 0; q < kPreBlocks * kBlkElems / 256; ++q) {
+        const int w = tid + 256 * q;
+        if (w < nb * kBlkElems) o4[w] = s4[w];
+    }
 }
 
 // High halves of two FP32 words: (a >> 16) | (b & 0xffff0000).
@@ -446,11 +459,11 @@ hipError_t launch_prescale_bf16x3(const sht_plan_s *p, const double *alm, void *
     const long long m0len = (p->mval[0] == 0) ? (p->lmax + 1) : 0;
     const int groups = (p->nmaps + 15) / 16;
     const long long nblocks = bf16_blocks(p);
-    const long long n = nblocks * 128;
-    dim3 grid((unsigned)((n + 255) / 256), (unsigned)groups);
-    hipLaunchKernelGGL(k_prescale_bf16x3, grid, dim3(256), 0, st,
+    const long long nwg = (nblocks + kPreBlocks - 1) / kPreBlocks;
+    if (nwg <= 0 || nwg > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_prescale_bf16x3, dim3((unsigned)nwg, (unsigned)groups), dim3(256), 0, st,
                        reinterpret_cast<const double2 *>(alm), p->d_cn, p->d_moff, p->d_mval,
-                       p->d_boff, p->nm, p->lmax, p->nalm, nblocks, p->nmaps, m0len,
+                       p->d_boff, p->d_bm32, p->lmax, p->nalm, nblocks, p->nmaps, m0len,
                        reinterpret_cast<v4u *>(Bb));
     return hipGetLastError();
 }

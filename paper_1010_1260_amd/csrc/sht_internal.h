@@ -132,6 +132,7 @@ struct sht_plan_s {
     double *d_cn;        // [nalm] normalisation c_lm folded into the coefficients
     int32_t *d_minv;     // [mmax + 1] index of m in the set, -1 if absent
     long long *d_boff;   // [nm] first 32-step block of each m (split-BF16 operand packing)
+    int32_t *d_bm32;     // [32-step blocks] index of the m that owns each block
     long long *d_boff16; // [nm] first 16-row block of each m (FP32 matrix-core operand packing)
     int32_t *d_bm16;     // [nblk16] index of the m that owns each 16-row block
     long long nblk16;    // 16-row blocks over all m

@@ -72,7 +72,8 @@ sht_status upload(T **dst, const std::vector<T> &src, size_t *acc)
 void free_tables(sht_plan_s *p)
 {
     void *ptrs[] = {p->d_pairs, p->d_mval, p->d_moff, p->d_mu, p->d_A, p->d_cn,
-                    p->d_minv, p->d_rings, p->d_pool, p->d_boff, p->d_boff16, p->d_bm16};
+                    p->d_minv, p->d_rings, p->d_pool, p->d_boff, p->d_boff16, p->d_bm16,
+                    p->d_bm32};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (int c = 0; c < sht::kNumRingClasses; ++c) {
@@ -82,6 +83,7 @@ void free_tables(sht_plan_s *p)
     p->d_pairs = nullptr; p->d_mval = nullptr; p->d_moff = nullptr; p->d_mu = nullptr;
     p->d_A = nullptr; p->d_cn = nullptr; p->d_minv = nullptr; p->d_rings = nullptr;
     p->d_pool = nullptr; p->d_boff = nullptr; p->d_boff16 = nullptr; p->d_bm16 = nullptr;
+    p->d_bm32 = nullptr;
 }
 
 sht_status check_plan(sht_plan_t p)
@@ -411,6 +413,14 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
             acc_b += (d->lmax - mval[i] + 1 + 31) / 32;
         }
         st = upload(&p->d_boff, boff, &tb);
+        if (st == SHT_OK) {
+            std::vector<int32_t> bm32((size_t)acc_b);
+            for (int i = 0; i < d->nm; ++i) {
+                const long long e = (i + 1 < d->nm) ? boff[i + 1] : acc_b;
+                for (long long b = boff[i]; b < e; ++b) bm32[(size_t)b] = i;
+            }
+            st = upload(&p->d_bm32, bm32, &tb);
+        }
     }
     if (st == SHT_OK) {
         std::vector<long long> boff16(d->nm);
