@@ -53,15 +53,18 @@ def _cpu_model() -> str:
 
 def recorded_traffic(key):
     """HBM bytes per launch recorded from rocprofv3 counters (profiles/traffic.json),
-    or None when absent or when the kernel source changed since."""
+    or None when absent or when the kernel's sources (its file and the headers
+    it includes, hashed together) changed since."""
     import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[key]
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-        if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
+        h = hashlib.sha256()
+        for s in rec["sources"]:
+            h.update(open(os.path.join(ROOT, s), "rb").read())
+        if h.hexdigest()[:16] != rec["sources_sha256_16"]:
             return None
         return float(rec["bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
+    except (OSError, KeyError, ValueError, TypeError):
         return None
 
 
