@@ -243,6 +243,9 @@ __device__ __forceinline__ void block32_dead(double x, double &ua, double &ub, i
 __device__ __forceinline__ void super_dma(char *buf, const v4u *__restrict__ Bm,
                                           const double *__restrict__ Am, int sb, int tid)
 {
+    // the lane addresses are recomputed at every copy (a few integer
+    // operations) rather than kept live, and spilled, across the loop
+    asm volatile("" : "+v"(tid));
     const v4u *src = Bm + (long long)sb * kSuper * kBlkElems;
     v4u *dst = reinterpret_cast<v4u *>(buf + kABytes);
 #pragma unroll
