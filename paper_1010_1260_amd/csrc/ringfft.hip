@@ -330,8 +330,10 @@ __device__ __attribute__((always_inline)) inline void ring_tables_load(const Rin
 // with E = DFT_len(x_{2j}) and O = DFT_len(x_{2j+1}) (Bluestein each, one
 // after the other in the same LDS buffer), X_j = E_j + w^j O_j and
 // X_{j+len} = E_j - w^j O_j, w = e^{sign 2 pi i / clen}.  The ring is even,
-// so TW holds the n-th roots with n = 2 clen: w^j = TW(2 j).
-template <int NT, int MAXN, bool REG>
+// so TW holds the n-th roots with n = 2 clen: w^j = TW(2 j).  PRIV: the
+// half kept across each Bluestein transform lives in private memory instead
+// of registers (for kernels whose register budget is already spent).
+template <int NT, int MAXN, bool REG, bool PRIV>
 __device__ __attribute__((always_inline)) inline void split_bluestein(
     double2 *buf, const RingDesc &d, int sign, const double2 *__restrict__ pool,
     const RingTables &rt, const Chirps<NT, MAXN, REG> &ch)
@@ -339,11 +341,9 @@ __device__ __attribute__((always_inline)) inline void split_bluestein(
     constexpr int QH = (MAXN / 2 + NT - 1) / NT;
     const int len = d.clen / 2;
     const int tid = threadIdx.x;
-    // keep and odd live in private memory (written once, read once per
-    // half), not in registers across the Bluestein transforms
     double2 keep[QH], odd[QH];
-    int zq = 0;
-    asm volatile("" : "+s"(zq));
+    int zq = 0;   // an opaque zero index keeps the arrays out of registers
+    if constexpr (PRIV) asm volatile("" : "+s"(zq));
 #pragma unroll
     for (int q = 0; q < QH; ++q) {
         const int j = tid + q * NT;
@@ -388,7 +388,7 @@ __device__ __attribute__((always_inline)) inline void split_bluestein(
     __syncthreads();
 }
 
-template <int NT, int MAXN, bool REG>
+template <int NT, int MAXN, bool REG, bool PRIV = false>
 __device__ __attribute__((always_inline)) inline void ring_dft(double2 *buf, const RingDesc &d, int sign,
                                 const double2 *__restrict__ pool, const RingTables &rt,
                                 const Chirps<NT, MAXN, REG> &ch)
@@ -396,7 +396,7 @@ __device__ __attribute__((always_inline)) inline void ring_dft(double2 *buf, con
     if (d.nb == 0) {
         fft_lds<NT, MAXN>(buf, d.clen, sign, rt.TW, (d.n % 2 == 0) ? 2 : 1);
     } else if (d.half) {
-        split_bluestein<NT, MAXN, REG>(buf, d, sign, pool, rt, ch);
+        split_bluestein<NT, MAXN, REG, PRIV>(buf, d, sign, pool, rt, ch);
     } else {
         bluestein_lds<NT, MAXN, REG>(buf, d.clen, d.nb, sign, ch, rt.TB, pool + d.bq);
     }
@@ -423,7 +423,7 @@ __device__ inline double2 load_mode(const double2 *__restrict__ drow, long long 
 // spectrum / FFT buffer, the twiddle tables and the alias staging slots
 // (RingLds).
 // Synthesis of one ring: drow = its Delta_m row, out = its first pixel.
-template <int NT, int MAXN, bool REG>
+template <int NT, int MAXN, bool REG, bool PRIV>
 __device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, const RingTables &rt, const RingDesc &d,
                            const double2 *__restrict__ pool, const double2 *__restrict__ drow,
                            long long dstride, const int *__restrict__ minv, int mcontig, int mmax,
@@ -584,7 +584,7 @@ __device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, c
             if (k2 != k) buf[k2] = Zk2;
         }
         __syncthreads();
-        ring_dft<NT, MAXN, REG>(buf, d, +1, pool, rt, ch);
+        ring_dft<NT, MAXN, REG, PRIV>(buf, d, +1, pool, rt, ch);
         if ((reinterpret_cast<uintptr_t>(out) & 15) == 0) {
             double2 *o2 = reinterpret_cast<double2 *>(out);
             for (int j = tid; j < h; j += NT) o2[j] = buf[j];
@@ -596,7 +596,7 @@ __device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, c
             }
         }
     } else {
-        ring_dft<NT, MAXN, REG>(buf, d, +1, pool, rt, ch);
+        ring_dft<NT, MAXN, REG, PRIV>(buf, d, +1, pool, rt, ch);
         for (int j = tid; j < n; j += NT) out[j] = buf[j].x;
     }
 }
@@ -614,7 +614,7 @@ __global__ __launch_bounds__(NT, 4) void k_ring_synth(
     const RingDesc d = rings[r];
     double2 *tw = buf + lds.fft_entries;
     const RingTables rt = {tw, tw + lds.tw_entries};
-    synth_ring<NT, MAXN, true>(buf, rt, d,
+    synth_ring<NT, MAXN, false, false>(buf, rt, d,
                                pool, delta + b * nm * nrings + r, nrings, minv, mcontig, mmax,
                                map + b * npix + d.start);
 }
@@ -632,7 +632,7 @@ __global__ __launch_bounds__(NT, 4) void k_ring_synth_batch(
     const double2 *delta = reinterpret_cast<const double2 *>(ws + bm.delta_off);
     double2 *tw = buf + lds.fft_entries;
     const RingTables rt = {tw, tw + lds.tw_entries};
-    synth_ring<NT, MAXN, false>(buf, rt, d,
+    synth_ring<NT, MAXN, false, true>(buf, rt, d,
                                 bm.pool, delta + it.y, bm.nrings, bm.minv, bm.mcontig,
                                 bm.mmax, outs[it.x] + d.start);
 }
