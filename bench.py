@@ -220,6 +220,25 @@ def main() -> int:
         alm0 = torch.from_numpy(alms_np[0]).to(dev).reshape(1, -1)
         wall, st, out = run_plan(plan64, alm0, args.steps, args.warmup, lib, hip, torch, np)
         fp64 = dict(plan=plan64, wall=wall, st=st, out=out)
+        # map2alm (quadrature-weighted analysis) of that map on the same plan:
+        # uniform pixel weight 4 pi / npix, no refinement and 3 refinement steps
+        w = torch.full((geom.nrings,), 4.0 * np.pi / geom.npix, dtype=torch.float64, device=dev)
+        a2m = {}
+        for niter in (0, 3):
+            plan64.map2alm(out, w, niter=niter)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(2):
+                back = plan64.map2alm(out, w, niter=niter)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 2
+            err = float(torch.linalg.norm(back - alm0) / torch.linalg.norm(alm0))
+            a2m[f"niter{niter}"] = {"ms": ms, "maps_per_s": 1e3 / ms, "rel_err_vs_alm": err}
+            del back
+        fp64["map2alm"] = a2m
     mixed = None
     if mixed_runs:
         best = max(mixed_runs, key=lambda k: 1.0 / mixed_runs[k]["wall"])
@@ -243,6 +262,7 @@ def main() -> int:
                                   "kernel": "k_legendre_fwd<2>",
                                   "flops_per_launch": flops},
             "fourier_GBps": fft_bytes_per_map / (float(fp64["st"][2]) * 1e-3) / 1e9,
+            "map2alm": fp64["map2alm"],
         }
         res["fp64"] = fp64_info
     if mixed is not None:

@@ -146,6 +146,28 @@ sht_status sht_plan_workspace_size(sht_plan_t plan, size_t *bytes);
 sht_status sht_alm2map(sht_plan_t plan, const double *alm, double *map,
                        void *ws, size_t ws_bytes, void *stream);
 
+/* map2alm (Eq. map2almDef, Sec. 2.1): the quadrature-weighted analysis
+ *     a_lm = sum_r w_r sum_j s_rj conj(Y_lm(theta_r, phi0_r + 2 pi j / nphi_r)),
+ * i.e. D * adjoint(w s) with D = 1 for m = 0 and 1/2 for m > 0 (the adjoint
+ * counts m and -m together).  On Gauss-Legendre rings with w_r the node
+ * weight times 2 pi / nphi_r, nrings > lmax and nphi_r > 2 lmax it inverts
+ * sht_alm2map exactly; on other grids it is the usual approximate analysis,
+ * refined by niter Jacobi steps a <- a + map2alm(s - alm2map(a)).
+ *   map          device float64 [nmaps][npix] (read; only ring pixels are used)
+ *   ring_weight  device float64 [nrings]: weight of one pixel of ring r
+ *   alm          device complex128 [nmaps][nalm] (written; Im of m = 0 is 0)
+ *   niter        0 .. SHT_MAX_MAP2ALM_ITER refinement steps
+ *   tmp_map      device float64 [nmaps][npix] scratch, required when niter > 0
+ *                (may be NULL otherwise); its contents are overwritten
+ *   ws           workspace of at least sht_plan_workspace_size bytes
+ * The refinement's alm2map runs in the plan's precision; the analysis is
+ * FP64.  Errors: SHT_ERR_INVALID_ARG for NULL pointers, niter out of range
+ * or a missing tmp_map; SHT_ERR_WORKSPACE for a short workspace. */
+#define SHT_MAX_MAP2ALM_ITER 100
+sht_status sht_map2alm(sht_plan_t plan, const double *map, const double *ring_weight,
+                       double *alm, int32_t niter, double *tmp_map, void *ws, size_t ws_bytes,
+                       void *stream);
+
 /* sht_alm2map that also records caller-created HIP events (hipEvent_t) on
  * `stream` at its stage boundaries, for stage timing:
  * events[0] before the coefficient prescale, events[1] before the Legendre

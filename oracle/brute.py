@@ -13,7 +13,10 @@ arithmetic.  The map is then the literal double sum of Eq. (alm2mapDef),
     s(theta, phi) = sum_{l <= lmax} sum_{m=-l}^{l} a_lm Y_lm(theta, phi),
 
 over every pixel, with a_{l,-m} = (-1)^m conj(a_lm) and
-Y_{l,-m} = (-1)^m P_lm e^{-i m phi} (Sec. 2.1).
+Y_{l,-m} = (-1)^m P_lm e^{-i m phi} (Sec. 2.1).  The analysis is the literal
+weighted sum of Eq. (map2almDef) with the conjugate harmonic,
+
+    a_lm = sum_pixels w_p s_p conj(Y_lm(theta_p, phi_p)),  m >= 0.
 """
 from __future__ import annotations
 
@@ -92,4 +95,23 @@ def alm2map_brute(lmax: int, geom, alm) -> np.ndarray:
         s0 = int(geom.ringstart[r])
         out[s0:s0 + n] = acc.real
         assert np.max(np.abs(acc.imag)) <= 1e-12 * max(1.0, np.max(np.abs(acc.real)))
+    return out
+
+
+def map2alm_brute(lmax: int, geom, m_in, ring_weight) -> np.ndarray:
+    """Literal weighted sum over every pixel (full m set), complex128 [nalm]."""
+    m_in = np.asarray(m_in, dtype=np.float64)
+    out = np.zeros((lmax + 1) * (lmax + 2) // 2, dtype=np.complex128)
+    for r in range(geom.nrings):
+        T = plm_table(lmax, geom.cth[r], geom.sth[r])
+        n = int(geom.nphi[r])
+        s0 = int(geom.ringstart[r])
+        phi = float(geom.phi0[r]) + 2.0 * np.pi * np.arange(n) / n
+        sw = float(ring_weight[r]) * m_in[s0:s0 + n]
+        off = 0
+        for m in range(lmax + 1):
+            e = np.sum(sw * np.exp(-1j * m * phi))
+            for l in range(m, lmax + 1):
+                out[off + (l - m)] += T[l, m] * e
+            off += lmax - m + 1
     return out

@@ -224,3 +224,24 @@ def alm2map_adjoint(lmax: int, geom, m_in, mval=None, nthreads: int = 0) -> np.n
         s0, n = int(geom.ringstart[r]), int(geom.nphi[r])
         dt[r] = ring_analysis(m_in[s0:s0 + n], mval, float(geom.phi0[r]))
     return delta_adjoint(lmax, mval, geom.cth, geom.sth, dt, nthreads)
+
+
+def map2alm(lmax: int, geom, m_in, ring_weight, niter: int = 0, mval=None,
+            nthreads: int = 0) -> np.ndarray:
+    """Quadrature-weighted analysis (Eq. map2almDef read with conj(Y_lm) and a
+    weight w_r per pixel of ring r): a = D adjoint(w s), D = 1 for m = 0 and
+    1/2 for m > 0 (the adjoint counts m and -m together), then `niter` Jacobi
+    steps a <- a + D adjoint(w (s - alm2map(a)))."""
+    mval = _mset(lmax, mval)
+    m_in = np.asarray(m_in, dtype=np.float64)
+    w = np.asarray(ring_weight, dtype=np.float64)
+    wpix = np.zeros(int(geom.npix))
+    for r in range(geom.nrings):
+        s0, n = int(geom.ringstart[r]), int(geom.nphi[r])
+        wpix[s0:s0 + n] = w[r]
+    dfac = np.concatenate([np.full(lmax - int(m) + 1, 1.0 if m == 0 else 0.5) for m in mval])
+    a = dfac * alm2map_adjoint(lmax, geom, wpix * m_in, mval, nthreads)
+    for _ in range(niter):
+        res = m_in - alm2map(lmax, geom, a, mval, nthreads)
+        a = a + dfac * alm2map_adjoint(lmax, geom, wpix * res, mval, nthreads)
+    return a

@@ -31,7 +31,8 @@ SHT_MAX_NPHI = 16384
 EXPORTED = [
     "sht_plan", "sht_plan_destroy", "sht_plan_get_info", "sht_plan_workspace_size",
     "sht_alm2map", "sht_alm2map_events", "sht_alm2map_adjoint", "sht_alm2delta", "sht_delta2map",
-    "sht_map2delta_adjoint", "sht_delta2alm_adjoint", "sht_status_string", "sht_version",
+    "sht_map2delta_adjoint", "sht_delta2alm_adjoint", "sht_map2alm", "sht_status_string",
+    "sht_version",
     "sht_plan_batch", "sht_batch_destroy", "sht_batch_workspace_size", "sht_alm2map_batch",
     "sht_batch_get_config", "sht_batch_set_config", "sht_batch_autotune",
     "sht_batch_graph_capture", "sht_batch_graph_launch",
@@ -105,9 +106,10 @@ def load(path: str | None = None):
     L.sht_delta2map.argtypes = [vp, vp, vp, vp]
     L.sht_map2delta_adjoint.argtypes = [vp, vp, vp, vp]
     L.sht_delta2alm_adjoint.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.sht_map2alm.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp, vp, ctypes.c_size_t, vp]
     for fn in ["sht_plan", "sht_plan_destroy", "sht_plan_get_info", "sht_plan_workspace_size",
                "sht_alm2map", "sht_alm2map_events", "sht_alm2map_adjoint", "sht_alm2delta", "sht_delta2map",
-               "sht_map2delta_adjoint", "sht_delta2alm_adjoint"]:
+               "sht_map2delta_adjoint", "sht_delta2alm_adjoint", "sht_map2alm"]:
         getattr(L, fn).restype = ctypes.c_int
     L.sht_plan_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int32]
     L.sht_batch_destroy.argtypes = [vp]

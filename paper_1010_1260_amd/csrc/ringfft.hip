@@ -638,13 +638,15 @@ __global__ __launch_bounds__(NT, 4) void k_ring_synth_batch(
 }
 
 // Analysis (adjoint of the synthesis): G_k by a real DFT, then
-// Dt_m = c_m e^{-i m phi0} G_{m mod n}.
+// Dt_m = c_m e^{-i m phi0} G_{m mod n} with c_0 = 1 and c_m = cfac for m > 0
+// (cfac = 2: the adjoint; cfac = 1: the quadrature analysis), times the
+// ring's pixel weight rw[r] when rw is given.
 template <int NT, int MAXN>
 __global__ __launch_bounds__(NT, 4) void k_ring_anal(
     const int *__restrict__ ids, const RingDesc *__restrict__ rings,
     const double2 *__restrict__ pool, const double *__restrict__ map, long long npix,
     const int *__restrict__ mval, int mcontig, int nm, int nrings, double2 *__restrict__ dt,
-    RingLds lds)
+    RingLds lds, const double *__restrict__ rw, double cfac)
 {
     extern __shared__ double2 buf[];
     const int r = ids[xcd_logical(blockIdx.x, gridDim.x)];
@@ -694,6 +696,7 @@ __global__ __launch_bounds__(NT, 4) void k_ring_anal(
         step = make_double2(cs, -sn);
     }
     bool first = true;
+    const double w = rw ? rw[r] : 1.0;
     for (int i = tid; i < nm; i += NT) {
         const int m = mval[i];
         const int kk = m % n;
@@ -711,8 +714,9 @@ __global__ __launch_bounds__(NT, 4) void k_ring_anal(
             v = make_double2(G.x, 0.0);
         } else {
             v = cmul(G, ph);
-            v.x *= 2.0; v.y *= 2.0;
+            v.x *= cfac; v.y *= cfac;
         }
+        if (rw) { v.x *= w; v.y *= w; }
         orow[(long long)i * nrings] = v;
     }
 }
@@ -761,7 +765,8 @@ hipError_t synth_class(const sht_plan_s *p, int c, const double2 *delta, double 
 }
 
 template <int NT, int MAXN>
-hipError_t anal_class(const sht_plan_s *p, int c, const double *map, double2 *dt, hipStream_t st)
+hipError_t anal_class(const sht_plan_s *p, int c, const double *map, double2 *dt, hipStream_t st,
+                      const double *rw, double cfac)
 {
     const RingClass &rc = p->cls[c];
     if (rc.count == 0) return hipSuccess;
@@ -771,7 +776,7 @@ hipError_t anal_class(const sht_plan_s *p, int c, const double *map, double2 *dt
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_ring_anal<NT, MAXN>), dim3((unsigned)rc.count, (unsigned)p->nmaps),
                        dim3(NT), lds, st, rc.d_ids, p->d_rings, p->d_pool, map, p->npix,
-                       p->d_mval, p->mcontig, p->nm, p->nrings, dt, rc.lds);
+                       p->d_mval, p->mcontig, p->nm, p->nrings, dt, rc.lds, rw, cfac);
     return hipGetLastError();
 }
 
@@ -789,12 +794,30 @@ hipError_t launch_ring_synth(const sht_plan_s *p, const double2 *delta, double *
     return e;
 }
 
-hipError_t launch_ring_anal(const sht_plan_s *p, const double *map, double2 *dt, hipStream_t st)
+hipError_t launch_ring_anal(const sht_plan_s *p, const double *map, double2 *dt, hipStream_t st,
+                            const double *rw, double cfac)
 {
-    hipError_t e = anal_class<1024, 8192>(p, 2, map, dt, st);
-    if (e == hipSuccess) e = anal_class<512, 4096>(p, 1, map, dt, st);
-    if (e == hipSuccess) e = anal_class<256, 2048>(p, 0, map, dt, st);
+    hipError_t e = anal_class<1024, 8192>(p, 2, map, dt, st, rw, cfac);
+    if (e == hipSuccess) e = anal_class<512, 4096>(p, 1, map, dt, st, rw, cfac);
+    if (e == hipSuccess) e = anal_class<256, 2048>(p, 0, map, dt, st, rw, cfac);
     return e;
+}
+
+// r = s - r over n doubles (residual of the refined analysis)
+__global__ __launch_bounds__(256) void k_residual(const double *__restrict__ s,
+                                                  double *__restrict__ r, long long n)
+{
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) r[i] = s[i] - r[i];
+}
+
+hipError_t launch_residual(const double *s, double *r, long long n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const long long nb = (n + 255) / 256;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_residual, dim3((unsigned)nb), dim3(256), 0, st, s, r, n);
+    return hipGetLastError();
 }
 
 template <int NT, int MAXN>

@@ -157,7 +157,7 @@ hipError_t launch_prescale(const sht_plan_s *p, const double *alm, double2 *ap, 
 hipError_t launch_legendre_fwd(const sht_plan_s *p, const double2 *ap, double2 *delta,
                                hipStream_t st);
 hipError_t launch_legendre_adj_ws(const sht_plan_s *p, const double2 *dt, double2 *part,
-                                  double *alm, hipStream_t st);
+                                  double *alm, hipStream_t st, bool accumulate = false);
 size_t adj_part_bytes(const sht_plan_s *p);
 size_t mfma_bf_bytes(const sht_plan_s *p);
 hipError_t launch_prescale_f32(const sht_plan_s *p, const double *alm, float *Bf, hipStream_t st);
@@ -170,7 +170,9 @@ hipError_t launch_legendre_mfma_bf16x3(const sht_plan_s *p, const void *Bb, doub
                                        hipStream_t st);
 hipError_t launch_ring_synth(const sht_plan_s *p, const double2 *delta, double *map,
                              hipStream_t st);
-hipError_t launch_ring_anal(const sht_plan_s *p, const double *map, double2 *dt, hipStream_t st);
+hipError_t launch_ring_anal(const sht_plan_s *p, const double *map, double2 *dt, hipStream_t st,
+                            const double *rw = nullptr, double cfac = 2.0);
+hipError_t launch_residual(const double *s, double *r, long long n, hipStream_t st);
 hipError_t launch_batch_legendre(const BatchMap *maps, int nmaps, long long max_nalm,
                                  const BatchTile *tiles, int ntiles, int chains, int grid_waves,
                                  const double *const *alms, void *ws, int *counter,

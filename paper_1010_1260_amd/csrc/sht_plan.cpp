@@ -613,4 +613,32 @@ sht_status sht_alm2map_adjoint(sht_plan_t p, const double *map, double *alm, voi
     return s;
 }
 
+sht_status sht_map2alm(sht_plan_t p, const double *map, const double *ring_weight, double *alm,
+                       int32_t niter, double *tmp_map, void *ws, size_t ws_bytes, void *stream)
+{
+    sht_status s = check_plan(p);
+    if (s != SHT_OK) return s;
+    if (!map || !alm || !ring_weight || niter < 0 || niter > SHT_MAX_MAP2ALM_ITER)
+        return SHT_ERR_INVALID_ARG;
+    if (niter > 0 && !tmp_map) return SHT_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < workspace_bytes(p)) return SHT_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    double2 *dt = (double2 *)ws;
+    double2 *part = (double2 *)((char *)ws + p->ws_delta_bytes);
+    double2 *delta = (double2 *)((char *)ws + p->ws_ap_bytes);
+    // a = D adjoint(w s): the analysis with c_m = 1 for every m
+    s = from_hip(sht::launch_ring_anal(p, map, dt, st, ring_weight, 1.0));
+    if (s == SHT_OK) s = from_hip(sht::launch_legendre_adj_ws(p, dt, part, alm, st, false));
+    // a <- a + D adjoint(w (s - alm2map(a)))
+    for (int it = 0; it < niter && s == SHT_OK; ++it) {
+        s = legendre_stage(p, alm, ws, delta, st, nullptr);
+        if (s == SHT_OK) s = from_hip(sht::launch_ring_synth(p, delta, tmp_map, st));
+        if (s == SHT_OK)
+            s = from_hip(sht::launch_residual(map, tmp_map, (long long)p->nmaps * p->npix, st));
+        if (s == SHT_OK) s = from_hip(sht::launch_ring_anal(p, tmp_map, dt, st, ring_weight, 1.0));
+        if (s == SHT_OK) s = from_hip(sht::launch_legendre_adj_ws(p, dt, part, alm, st, true));
+    }
+    return s;
+}
+
 }  // extern "C"

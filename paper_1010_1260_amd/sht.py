@@ -148,6 +148,26 @@ class Plan:
                 "sht_alm2map_adjoint")
         return out
 
+    def map2alm(self, m: torch.Tensor, ring_weight, niter: int = 0,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+        """Quadrature-weighted analysis (sht_map2alm): D adjoint(w s), refined
+        by `niter` steps a <- a + map2alm(s - alm2map(a)).  ring_weight: the
+        weight of one pixel of each ring (float64 [nrings])."""
+        mm = self._map_in(m)
+        w = torch.as_tensor(ring_weight, dtype=torch.float64).to(self.device).contiguous()
+        if tuple(w.shape) != (self.nrings,):
+            raise ValueError("ring_weight must have one entry per ring")
+        out = torch.empty((self.nmaps, self.nalm), dtype=torch.complex128,
+                          device=self.device) if out is None else out
+        tmp = torch.empty((self.nmaps, self.npix), dtype=torch.float64,
+                          device=self.device) if niter > 0 else None
+        ws = self.workspace()
+        L.check(L.load().sht_map2alm(self._h, _ptr(mm), _ptr(w), _ptr(out), int(niter),
+                                     None if tmp is None else _ptr(tmp), _ptr(ws), ws.numel(),
+                                     ctypes.c_void_p(_cur_stream(self.device))),
+                "sht_map2alm")
+        return out
+
     def alm2delta(self, alm: torch.Tensor) -> torch.Tensor:
         a = self._alm_in(alm)
         out = torch.empty((self.nmaps, self.nm, self.nrings), dtype=torch.complex128,
