@@ -164,24 +164,20 @@ sht_status sht_plan_batch(sht_batch_t *out, const sht_plan_t *plans, int32_t n)
                       hipMemcpyHostToDevice) != hipSuccess)
             st = SHT_ERR_OOM;
     }
-    // Fourier work items per ring size class, longest rings first
+    // Fourier work items per ring size class, map by map and ring by ring:
+    // the workgroups that run together then read neighbouring rings of one
+    // map, whose Delta entries share cache lines
     for (int c = 0; c < sht::kNumRingClasses && st == SHT_OK; ++c) {
         std::vector<int2> items;
         sht::RingLds lds = {};
-        std::vector<std::pair<int, int2>> keyed;
         for (int i = 0; i < n; ++i) {
             const sht_plan_s *p = plans[i];
             for (int r = 0; r < p->nrings; ++r)
                 if (p->ring_class[r] == c) {
-                    keyed.push_back({p->ring_need[r], make_int2(i, r)});
+                    items.push_back(make_int2(i, r));
                     sht::ring_lds_add(lds, c, p->ring_n[r], p->ring_nb[r], p->ring_need[r]);
                 }
         }
-        std::stable_sort(keyed.begin(), keyed.end(),
-                         [](const std::pair<int, int2> &a, const std::pair<int, int2> &c) {
-                             return a.first > c.first;
-                         });
-        for (auto &kv : keyed) items.push_back(kv.second);
         b->cls[c].count = (int)items.size();
         b->cls[c].lds = lds;
         if (!items.empty() &&

@@ -54,19 +54,33 @@ struct Chains {
 };
 
 // One m of an m-pair for CH chains per lane: forward accumulation.
-template <int CH>
+template <int CH, bool CAS>
 __device__ inline void fwd_one_m(const Chains<CH> &g, const double (&s)[CH], int m, int i,
                                  long long off, double mum, int lmax,
                                  const double *__restrict__ A, const double2 *__restrict__ ap,
                                  double2 *__restrict__ delta, long long dbase, int nrings)
 {
     const int len = lmax - m + 1;
-    const double *__restrict__ Am = A + off;
-    const double2 *__restrict__ am = ap + off;
+    // The coefficients are only read here and their addresses are uniform
+    // across the wave.  CAS: read them through the constant address space,
+    // so that they come in by scalar loads also when the kernel stores Delta
+    // into the same buffer (the batched kernel's workspace), where the
+    // compiler cannot prove that the loads are not clobbered.
+    typedef const double __attribute__((address_space(4))) *CDp;
+    const double *__restrict__ Ag = A + off;
+    const double2 *__restrict__ apg = ap + off;
+    const CDp Ac = (CDp)(A + off);
+    const CDp amd = (CDp)(ap + off);   // a'_lm as (re, im) pairs
+    auto Am = [&](int k) -> double {
+        if constexpr (CAS) return Ac[k]; else return Ag[k];
+    };
+    auto am = [&](int k) -> double2 {
+        if constexpr (CAS) return make_double2(amd[2 * k], amd[2 * k + 1]); else return apg[k];
+    };
     double u0[CH], u1[CH], Er[CH], Ei[CH], Or[CH], Oi[CH];
     int k[CH];
     {
-        const double2 a0 = am[0];
+        const double2 a0 = am(0);
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             seed_mm(mum, s[c], m, u0[c], k[c]);
@@ -76,8 +90,8 @@ __device__ inline void fwd_one_m(const Chains<CH> &g, const double (&s)[CH], int
         }
     }
     if (len >= 2) {
-        const double A1 = Am[1];
-        const double2 a1 = am[1];
+        const double A1 = Am(1);
+        const double2 a1 = am(1);
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             u1[c] = (A1 * g.x[c]) * u0[c];
@@ -89,8 +103,8 @@ __device__ inline void fwd_one_m(const Chains<CH> &g, const double (&s)[CH], int
     for (; j + 8 <= len; j += 8) {
 #pragma unroll
         for (int t = 0; t < 8; t += 2) {
-            const double Aa = Am[j + t], Ab = Am[j + t + 1];
-            const double2 aa = am[j + t], ab = am[j + t + 1];
+            const double Aa = Am(j + t), Ab = Am(j + t + 1);
+            const double2 aa = am(j + t), ab = am(j + t + 1);
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const double u2 = fma(Aa * g.x[c], u1[c], -u0[c]);
@@ -113,8 +127,8 @@ __device__ inline void fwd_one_m(const Chains<CH> &g, const double (&s)[CH], int
         }
     }
     for (; j < len; ++j) {
-        const double Aa = Am[j];
-        const double2 aa = am[j];
+        const double Aa = Am(j);
+        const double2 aa = am(j);
         if (j & 1) {
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
@@ -178,7 +192,7 @@ __global__ __launch_bounds__(64) void k_legendre_fwd(
     for (int t = 0; t < 2; ++t) {
         const int i = (t == 0) ? q : nm - 1 - q;
         if (t == 1 && i == q) break;
-        fwd_one_m<CH>(g, s, mval[i], i, moff[i], mu[i], lmax, A, apb, delta, dbase, nrings);
+        fwd_one_m<CH, false>(g, s, mval[i], i, moff[i], mu[i], lmax, A, apb, delta, dbase, nrings);
     }
 }
 
@@ -377,7 +391,10 @@ __global__ __launch_bounds__(64) void k_legendre_fwd_batch(const BatchTile *__re
     for (;;) {
         int t = 0;
         if (lane == 0) t = atomicAdd(counter, 1);
-        t = __shfl(t, 0);
+        // wave-uniform tile index: the tile, its plan's tables and every
+        // coefficient of the recurrence then come through scalar loads, as
+        // in the single-plan kernel
+        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
         if (t >= ntiles) break;
         const BatchTile tile = tiles[t];
         const BatchMap &bm = maps[tile.map];
@@ -396,11 +413,17 @@ __global__ __launch_bounds__(64) void k_legendre_fwd_batch(const BatchTile *__re
         const double2 *ap = reinterpret_cast<const double2 *>(ws + bm.ap_off);
         double2 *delta = reinterpret_cast<double2 *>(ws + bm.delta_off);
         const int q = tile.mpair;
+        // the plan's per-m tables are read through the constant address
+        // space (wave-uniform, never written here): scalar loads, so the
+        // offsets and with them every coefficient address stay uniform
+        typedef const int __attribute__((address_space(4))) *CIp;
+        typedef const long long __attribute__((address_space(4))) *CLp;
+        typedef const double __attribute__((address_space(4))) *CDp;
         for (int u = 0; u < 2; ++u) {
             const int i = (u == 0) ? q : bm.nm - 1 - q;
             if (u == 1 && i == q) break;
-            fwd_one_m<CH>(g, s, bm.mval[i], i, bm.moff[i], bm.mu[i], bm.lmax, bm.A, ap, delta, 0,
-                          bm.nrings);
+            fwd_one_m<CH, true>(g, s, ((CIp)bm.mval)[i], i, ((CLp)bm.moff)[i], ((CDp)bm.mu)[i],
+                          bm.lmax, bm.A, ap, delta, 0, bm.nrings);
         }
     }
 }
