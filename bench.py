@@ -154,6 +154,41 @@ def run_uneven(args, torch, np, W, dev):
             "tuned_chains_waves_per_cu": list(cfg), "autotune_s": tune_s}
 
 
+def run_grad(args, torch, np, W, dev):
+    """The differentiation workload: 8 maps, l_max 1024, nside 512, loss
+    0.5 ||alm2map(a) - d||^2 with d ~ N(0, 1) per pixel; one step = forward
+    transform, loss, backward through the hand-written adjoint."""
+    from paper_1010_1260_amd import Plan, alm2map
+    c = W.CONFIGS[5]
+    L, N, B = c["lmax"], c["nside"], c["nmaps"]
+    geom = W.healpix_geometry(N)
+    plan = Plan(L, geom, nmaps=B, device=dev)
+    a0 = torch.from_numpy(np.stack([W.config_alm(5, i) for i in range(B)])).to(dev)
+    d = torch.from_numpy(np.stack([W.random_map(geom.npix, [5, 100 + i])
+                                   for i in range(B)])).to(dev)
+
+    def step():
+        a = a0.clone().requires_grad_(True)
+        loss = 0.5 * ((alm2map(a, plan) - d) ** 2).sum()
+        loss.backward()
+        return a.grad
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    n = 5
+    for _ in range(n):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n
+    return {"maps": B, "lmax": L, "nside": N, "ms_forward_backward": ms,
+            "maps_per_s": B / (ms * 1e-3)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,6 +367,8 @@ def main() -> int:
 
     if args.uneven:
         res["uneven_batch"] = run_uneven(args, torch, np, W, dev)
+    if args.only in ("all", "fp64"):
+        res["differentiation"] = run_grad(args, torch, np, W, dev)
 
     if not args.no_cpu_baseline:
         from oracle import ref
