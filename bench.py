@@ -209,8 +209,8 @@ def main() -> int:
                     help="oracle timed on every k-th ring (bounded CPU sample)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
-              "multi-GPU sharding is described in DESIGN.md, not implemented", file=sys.stderr)
+        print(f"bench.py: the transform runs on one GPU (--gpus {args.gpus} requested); "
+              "sharding over maps or ring pairs across GPUs is not implemented", file=sys.stderr)
         return 2
 
     import numpy as np
