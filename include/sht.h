@@ -36,8 +36,9 @@
  *  - sht_alm2map* and sht_alm2map_adjoint* only enqueue kernels on `stream`
  *    (a hipStream_t; NULL is the null stream).  They never allocate memory
  *    and never synchronise, so they can be captured into a HIP graph.
- *  - A plan is immutable after creation.  Calls on different streams are
- *    safe if they use distinct workspaces.
+ *  - A plan is immutable after creation, apart from its launch shape
+ *    (sht_plan_set_config, sht_plan_autotune), which changes no result.
+ *    Calls on different streams are safe if they use distinct workspaces.
  *
  * Errors: every call returns an sht_status; nothing throws across the ABI.
  * Argument errors are detected on the host before anything is enqueued.
@@ -100,6 +101,11 @@ typedef struct {
     int32_t nmaps;            /* maps per call, >= 1                                */
     int32_t precision;        /* sht_precision                                      */
     uint32_t flags;           /* SHT_FLAG_*                                         */
+    int64_t npix;             /* pixels per map in the caller's map buffers (the
+                                 stride between maps); 0 = max(ringstart + nphi).
+                                 Larger values let a plan over part of the rings
+                                 (a latitude band, one shard of ring pairs) write
+                                 into a full-sky map.  Smaller: SHT_ERR_INVALID_ARG */
 } sht_geometry_desc;
 
 /* Treat every ring on its own even when its mirror ring (cth negated
@@ -108,7 +114,7 @@ typedef struct {
 
 typedef struct {
     int64_t nalm;             /* complex coefficients per map                       */
-    int64_t npix;             /* pixels per map (max of ringstart + nphi)           */
+    int64_t npix;             /* pixels per map (desc.npix, else max of ringstart + nphi) */
     int32_t nrings;
     int32_t npairs;           /* recurrence units: mirror pairs + unpaired rings    */
     int32_t nm;
@@ -138,6 +144,27 @@ sht_status sht_plan_get_info(sht_plan_t plan, sht_plan_info *info);
 
 /* Bytes of device workspace sht_alm2map and sht_alm2map_adjoint need. */
 sht_status sht_plan_workspace_size(sht_plan_t plan, size_t *bytes);
+
+/* Launch shape of an FP64 plan's forward Legendre kernel: chains = ring
+ * pairs per lane (1, 2 or 4).  The best shape depends on the input size
+ * (Sec. 5, which proposes tuning per size): sht_plan picks a default from a
+ * table measured over sizes on MI355X.  Results do not depend on it (every
+ * ring pair runs the same arithmetic); only the time does.
+ * sht_plan_set_config: SHT_ERR_INVALID_ARG for other values,
+ * SHT_ERR_UNSUPPORTED on mixed-precision plans (their kernels have no such
+ * choice) or when the launch would exceed the grid limit.  Do not change the
+ * shape while another host thread enqueues work on the same plan. */
+sht_status sht_plan_get_config(sht_plan_t plan, int32_t *chains);
+sht_status sht_plan_set_config(sht_plan_t plan, int32_t chains);
+
+/* Autotuner of the launch shape above: times sht_alm2map at every chain
+ * count on the given buffers (alm read, map overwritten, ws as for
+ * sht_alm2map; synchronises `stream`) and keeps the fastest.  If cache_path
+ * is not NULL, a line "<plan signature> <chains> <ms>" is looked up first
+ * (no timing if found) and appended after tuning.  On mixed-precision plans
+ * it does nothing and returns SHT_OK. */
+sht_status sht_plan_autotune(sht_plan_t plan, const double *alm, double *map, void *ws,
+                             size_t ws_bytes, const char *cache_path, void *stream);
 
 /* alm2map (Eq. alm2mapDef): alm device complex128 [nmaps][nalm] (read),
  * map device float64 [nmaps][npix] (written at every ring pixel; pixels not

@@ -30,6 +30,7 @@ SHT_MAX_NPHI = 16384
 
 EXPORTED = [
     "sht_plan", "sht_plan_destroy", "sht_plan_get_info", "sht_plan_workspace_size",
+    "sht_plan_get_config", "sht_plan_set_config", "sht_plan_autotune",
     "sht_alm2map", "sht_alm2map_events", "sht_alm2map_adjoint", "sht_alm2delta", "sht_delta2map",
     "sht_map2delta_adjoint", "sht_delta2alm_adjoint", "sht_map2alm", "sht_status_string",
     "sht_version",
@@ -53,6 +54,7 @@ class GeometryDesc(ctypes.Structure):
         ("nmaps", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
+        ("npix", ctypes.c_int64),
     ]
 
 
@@ -92,6 +94,12 @@ def load(path: str | None = None):
         raise ImportError(
             f"{p} is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
             "(hipcc --offload-arch=gfx950); the transform has no CPU implementation")
+    # torch ships its own HIP runtime (same soname as the system one).  Load
+    # it first so that libsht.so binds to it: loaded the other way round the
+    # process holds two runtimes, and torch's memory and streams are foreign
+    # to the library's.
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(p)
     vp = ctypes.c_void_p
     L.sht_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(GeometryDesc)]
@@ -107,9 +115,13 @@ def load(path: str | None = None):
     L.sht_map2delta_adjoint.argtypes = [vp, vp, vp, vp]
     L.sht_delta2alm_adjoint.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp]
     L.sht_map2alm.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp, vp, ctypes.c_size_t, vp]
+    L.sht_plan_get_config.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.sht_plan_set_config.argtypes = [vp, ctypes.c_int32]
+    L.sht_plan_autotune.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_char_p, vp]
     for fn in ["sht_plan", "sht_plan_destroy", "sht_plan_get_info", "sht_plan_workspace_size",
                "sht_alm2map", "sht_alm2map_events", "sht_alm2map_adjoint", "sht_alm2delta", "sht_delta2map",
-               "sht_map2delta_adjoint", "sht_delta2alm_adjoint", "sht_map2alm"]:
+               "sht_map2delta_adjoint", "sht_delta2alm_adjoint", "sht_map2alm",
+               "sht_plan_get_config", "sht_plan_set_config", "sht_plan_autotune"]:
         getattr(L, fn).restype = ctypes.c_int
     L.sht_plan_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int32]
     L.sht_batch_destroy.argtypes = [vp]

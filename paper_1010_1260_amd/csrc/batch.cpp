@@ -56,6 +56,7 @@ int chain_index(int c) { return c == 1 ? 0 : (c == 2 ? 1 : 2); }
 sht_status check_batch(sht_batch_t b)
 {
     if (!b || b->magic != kBatchMagic) return SHT_ERR_BAD_HANDLE;
+    sht::clear_stale_error();
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return SHT_ERR_HIP;
     if (dev != b->device) return SHT_ERR_INVALID_ARG;
@@ -94,6 +95,7 @@ sht_status sht_plan_batch(sht_batch_t *out, const sht_plan_t *plans, int32_t n)
     if (!out) return SHT_ERR_INVALID_ARG;
     *out = nullptr;
     if (!plans || n < 1) return SHT_ERR_INVALID_ARG;
+    sht::clear_stale_error();
     int dev = -1;
     for (int i = 0; i < n; ++i) {
         const sht_plan_s *p = plans[i];

@@ -428,7 +428,6 @@ __global__ __launch_bounds__(64) void k_legendre_fwd_batch(const BatchTile *__re
     }
 }
 
-constexpr int kFwdChains = 2;
 // The adjoint reduces every 16 l-rows over the wave's lanes through LDS;
 // eight ring pairs per lane make that reduction small next to the
 // recurrence (2.4x faster than two pairs per lane at l_max 4096).
@@ -445,7 +444,11 @@ hipError_t launch_prescale(const sht_plan_s *p, const double *alm, double2 *ap, 
     return hipGetLastError();
 }
 
-int fwd_pblocks(const sht_plan_s *p) { return (p->npairs + 64 * kFwdChains - 1) / (64 * kFwdChains); }
+int fwd_pblocks(const sht_plan_s *p)
+{
+    const int per = 64 * p->fwd_chains;
+    return (p->npairs + per - 1) / per;
+}
 int adj_pblocks(const sht_plan_s *p) { return (p->npairs + 64 * kAdjChains - 1) / (64 * kAdjChains); }
 
 hipError_t launch_legendre_fwd(const sht_plan_s *p, const double2 *ap, double2 *delta,
@@ -455,7 +458,12 @@ hipError_t launch_legendre_fwd(const sht_plan_s *p, const double2 *ap, double2 *
     const int nmpairs = (p->nm + 1) / 2;
     const long long total = (long long)pblocks * nmpairs * p->nmaps;
     if (total <= 0 || total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_legendre_fwd<kFwdChains>, dim3((unsigned)total), dim3(64), 0, st,
+    auto kern = p->fwd_chains == 1   ? k_legendre_fwd<1>
+                : p->fwd_chains == 2 ? k_legendre_fwd<2>
+                : p->fwd_chains == 4 ? k_legendre_fwd<4>
+                                     : nullptr;
+    if (!kern) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(64), 0, st,
                        p->d_pairs, p->npairs, pblocks, p->d_mval, p->d_moff, p->d_mu, p->nm,
                        nmpairs, p->lmax, p->d_A, ap, p->nalm, delta, p->nrings, total);
     return hipGetLastError();

@@ -146,16 +146,25 @@ struct sht_plan_s {
     std::vector<int> ring_n;      // pixels of each ring
     std::vector<int> ring_nb;     // Bluestein length of each ring (0: none)
     sht::RingClass cls[sht::kNumRingClasses];
+    int fwd_chains;      // ring pairs per lane of the FP64 forward Legendre kernel (1, 2, 4)
+    int num_cus;         // compute units of the plan's device
     size_t ws_ap_bytes;  // workspace: prescaled coefficients
     size_t ws_delta_bytes;
 };
 
 namespace sht {
 
+// hipGetLastError returns the error of any earlier HIP call on the thread,
+// the caller's own included (a failed query a framework ignored, say).  Each
+// entry point clears it first, so that the launch checks below report only
+// the entry point's own launches.
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
 // Launchers (legendre.hip / ringfft.hip).  All enqueue on `st` only.
 hipError_t launch_prescale(const sht_plan_s *p, const double *alm, double2 *ap, hipStream_t st);
 hipError_t launch_legendre_fwd(const sht_plan_s *p, const double2 *ap, double2 *delta,
                                hipStream_t st);
+int fwd_pblocks(const sht_plan_s *p);
 hipError_t launch_legendre_adj_ws(const sht_plan_s *p, const double2 *dt, double2 *part,
                                   double *alm, hipStream_t st, bool accumulate = false);
 size_t adj_part_bytes(const sht_plan_s *p);

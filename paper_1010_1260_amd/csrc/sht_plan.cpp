@@ -8,8 +8,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <new>
+#include <sstream>
+#include <string>
 #include <unordered_map>
 #include <utility>
 #include <vector>
@@ -54,6 +57,33 @@ struct PairKeyHash {
     }
 };
 
+// Default launch shape of the FP64 forward Legendre kernel by problem size.
+// The best block shape depends on the input size (Sec. 5 finds no single
+// segment length / thread count best for every size and proposes tuning per
+// size), so the default comes from a table measured over sizes and
+// sht_plan_autotune can refine it per plan.  Key: the waves the launch would
+// have with one ring pair per lane, per compute unit.  More pairs per lane
+// give each wave independent recurrences to interleave but fewer waves to
+// hide latency with.  Measured on MI355X (256 compute units) over
+// l_max = 64..4096, nside = l_max / 2, 1..16 maps, with tune_fp64_chains.py.
+struct ChainRule {
+    double max_waves_per_cu;
+    int chains;
+};
+constexpr ChainRule kFwdChainTable[] = {
+    {32.0, 1},
+    {1e300, 2},
+};
+
+int default_fwd_chains(const sht_plan_s *p)
+{
+    const double waves1 = (double)((p->npairs + 63) / 64) * (double)((p->nm + 1) / 2) *
+                          (double)p->nmaps / (double)std::max(1, p->num_cus);
+    for (const ChainRule &r : kFwdChainTable)
+        if (waves1 <= r.max_waves_per_cu) return r.chains;
+    return 2;
+}
+
 template <class T>
 sht_status upload(T **dst, const std::vector<T> &src, size_t *acc)
 {
@@ -90,6 +120,7 @@ sht_status check_plan(sht_plan_t p)
 {
     if (!p) return SHT_ERR_BAD_HANDLE;
     if (p->magic != sht::kPlanMagic) return SHT_ERR_BAD_HANDLE;
+    sht::clear_stale_error();
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return SHT_ERR_HIP;
     if (dev != p->device) return SHT_ERR_INVALID_ARG;
@@ -238,6 +269,7 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     if (d->precision != SHT_FP64 && d->precision != SHT_FP32_MFMA &&
         d->precision != SHT_BF16X3_MFMA)
         return SHT_ERR_UNSUPPORTED;
+    sht::clear_stale_error();
     std::vector<int32_t> mval(d->nm);
     for (int i = 0; i < d->nm; ++i) {
         mval[i] = d->mval ? d->mval[i] : i;
@@ -273,6 +305,8 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
             npix = std::max(npix, start[r] + (long long)d->nphi[r]);
         }
     }
+    if (d->npix < 0 || (d->npix > 0 && d->npix < npix)) return SHT_ERR_INVALID_ARG;
+    if (d->npix > 0) npix = d->npix;
     // ---- Fourier classification per ring
     std::vector<RingDesc> rings(R);
     std::vector<int> ring_class(R);
@@ -320,6 +354,12 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     p->nmaps = d->nmaps;
     p->precision = d->precision;
     p->flags = d->flags;
+    p->num_cus = 0;
+    if (hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, p->device) !=
+        hipSuccess) {
+        delete p;
+        return SHT_ERR_HIP;
+    }
     p->npix = npix;
     p->mval = mval;
     p->moff.resize(d->nm + 1);
@@ -481,6 +521,7 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
                                           : (size_t)p->nmaps * (size_t)p->nalm * sizeof(double2),
         256);
     p->ws_delta_bytes = align_up((size_t)p->nmaps * (size_t)R * (size_t)p->nm * sizeof(double2), 256);
+    p->fwd_chains = default_fwd_chains(p);
     p->magic = sht::kPlanMagic;
     *out = p;
     return SHT_OK;
@@ -558,6 +599,87 @@ sht_status sht_alm2map(sht_plan_t p, const double *alm, double *map, void *ws, s
     s = legendre_stage(p, alm, ws, delta, st, nullptr);
     if (s == SHT_OK) s = from_hip(sht::launch_ring_synth(p, delta, map, st));
     return s;
+}
+
+sht_status sht_plan_get_config(sht_plan_t p, int32_t *chains)
+{
+    sht_status s = check_plan(p);
+    if (s != SHT_OK) return s;
+    if (!chains) return SHT_ERR_INVALID_ARG;
+    *chains = p->fwd_chains;
+    return SHT_OK;
+}
+
+sht_status sht_plan_set_config(sht_plan_t p, int32_t chains)
+{
+    sht_status s = check_plan(p);
+    if (s != SHT_OK) return s;
+    if (p->precision != SHT_FP64) return SHT_ERR_UNSUPPORTED;
+    if (chains != 1 && chains != 2 && chains != 4) return SHT_ERR_INVALID_ARG;
+    const long long pblocks = (p->npairs + 64LL * chains - 1) / (64LL * chains);
+    if (pblocks * ((p->nm + 1) / 2) * p->nmaps > 0x7fffffffLL) return SHT_ERR_UNSUPPORTED;
+    p->fwd_chains = chains;
+    return SHT_OK;
+}
+
+sht_status sht_plan_autotune(sht_plan_t p, const double *alm, double *map, void *ws,
+                             size_t ws_bytes, const char *cache_path, void *stream)
+{
+    sht_status s = check_plan(p);
+    if (s != SHT_OK) return s;
+    if (!alm || !map) return SHT_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < workspace_bytes(p)) return SHT_ERR_WORKSPACE;
+    if (p->precision != SHT_FP64) return SHT_OK;   // nothing to tune
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) return SHT_ERR_HIP;
+    std::ostringstream sig;
+    sig << prop.gcnArchName << "|fp64fwd|" << p->lmax << ":" << p->nm << ":" << p->mmax << ":"
+        << p->nrings << ":" << p->npairs << ":" << p->npix << ":" << p->nmaps;
+    const std::string key = sig.str();
+    // cache: one line per tuned plan, "<signature> <chains> <ms per transform>"
+    if (cache_path && cache_path[0]) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream ls(line);
+            std::string k;
+            int ch = 0;
+            double ms = 0;
+            if ((ls >> k >> ch >> ms) && k == key && sht_plan_set_config(p, ch) == SHT_OK)
+                return SHT_OK;
+        }
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return SHT_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return SHT_ERR_HIP; }
+    const int start = p->fwd_chains;
+    float best = 1e30f;
+    int best_ch = start;
+    for (int ch : {1, 2, 4}) {
+        if (sht_plan_set_config(p, ch) != SHT_OK) continue;
+        s = sht_alm2map(p, alm, map, ws, ws_bytes, stream);   // warm-up
+        if (s != SHT_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { s = SHT_ERR_HIP; break; }
+        for (int r = 0; r < 3 && s == SHT_OK; ++r) s = sht_alm2map(p, alm, map, ws, ws_bytes, stream);
+        if (s != SHT_OK || hipEventRecord(e1, st) != hipSuccess ||
+            hipEventSynchronize(e1) != hipSuccess) {
+            s = s == SHT_OK ? SHT_ERR_HIP : s;
+            break;
+        }
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { s = SHT_ERR_HIP; break; }
+        if (ms < best) { best = ms; best_ch = ch; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->fwd_chains = (s == SHT_OK) ? best_ch : start;
+    if (s != SHT_OK) return s;
+    if (cache_path && cache_path[0]) {
+        std::ofstream outf(cache_path, std::ios::app);
+        if (outf) outf << key << " " << best_ch << " " << best / 3 << "\n";
+    }
+    return SHT_OK;
 }
 
 sht_status sht_alm2map_events(sht_plan_t p, const double *alm, double *map, void *ws,

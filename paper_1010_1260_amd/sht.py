@@ -63,6 +63,7 @@ class Plan:
         self.precision = precision
         d.precision = self.PRECISIONS[precision]
         d.flags = 0 if pairing else L.SHT_FLAG_NO_PAIRING
+        d.npix = int(getattr(geom, "npix", 0) or 0)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             L.check(lib.sht_plan(ctypes.byref(h), ctypes.byref(d)), "sht_plan")
@@ -105,6 +106,29 @@ class Plan:
                                    device=self.device)
         return self._ws
 
+    @property
+    def config(self) -> int:
+        """Ring pairs per lane of the FP64 forward Legendre kernel."""
+        c = ctypes.c_int32()
+        L.check(L.load().sht_plan_get_config(self._h, ctypes.byref(c)), "sht_plan_get_config")
+        return int(c.value)
+
+    def set_config(self, chains: int):
+        L.check(L.load().sht_plan_set_config(self._h, chains), "sht_plan_set_config")
+
+    def autotune(self, alm: torch.Tensor, out: torch.Tensor | None = None,
+                 cache_path: str | None = None) -> int:
+        """Time every launch shape on these buffers and keep the fastest."""
+        a = self._alm_in(alm)
+        out = self._new_map() if out is None else \
+            self._check_out(out, torch.float64, self.nmaps * self.npix, "out")
+        ws = self.workspace()
+        cp = cache_path.encode() if cache_path else None
+        L.check(L.load().sht_plan_autotune(self._h, _ptr(a), _ptr(out), _ptr(ws), ws.numel(),
+                                           cp, ctypes.c_void_p(_cur_stream(self.device))),
+                "sht_plan_autotune")
+        return self.config
+
     def _alm_in(self, alm: torch.Tensor) -> torch.Tensor:
         if alm.dtype != torch.complex128:
             raise TypeError("alm must be complex128")
@@ -125,6 +149,15 @@ class Plan:
             raise ValueError(f"map must have shape ({self.nmaps}, {self.npix})")
         return mm.contiguous()
 
+    def _check_out(self, out: torch.Tensor, dtype, numel: int, what: str) -> torch.Tensor:
+        """A caller-supplied output must match exactly: the kernels write
+        through its raw pointer."""
+        if out.dtype != dtype or out.device != self.device or not out.is_contiguous() \
+                or out.numel() != numel:
+            raise ValueError(f"{what} must be a contiguous {dtype} tensor of {numel} elements "
+                             f"on {self.device}")
+        return out
+
     def _new_map(self) -> torch.Tensor:
         f = torch.empty if self._full_cover else torch.zeros
         return f((self.nmaps, self.npix), dtype=torch.float64, device=self.device)
@@ -132,7 +165,8 @@ class Plan:
     # ---------------------------------------------------------- transforms
     def alm2map(self, alm: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         a = self._alm_in(alm)
-        out = self._new_map() if out is None else out
+        out = self._new_map() if out is None else \
+            self._check_out(out, torch.float64, self.nmaps * self.npix, "out")
         ws = self.workspace()
         L.check(L.load().sht_alm2map(self._h, _ptr(a), _ptr(out), _ptr(ws), ws.numel(),
                                      ctypes.c_void_p(_cur_stream(self.device))), "sht_alm2map")
@@ -141,7 +175,8 @@ class Plan:
     def alm2map_adjoint(self, m: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         mm = self._map_in(m)
         out = torch.empty((self.nmaps, self.nalm), dtype=torch.complex128,
-                          device=self.device) if out is None else out
+                          device=self.device) if out is None else \
+            self._check_out(out, torch.complex128, self.nmaps * self.nalm, "out")
         ws = self.workspace()
         L.check(L.load().sht_alm2map_adjoint(self._h, _ptr(mm), _ptr(out), _ptr(ws), ws.numel(),
                                              ctypes.c_void_p(_cur_stream(self.device))),
@@ -158,7 +193,8 @@ class Plan:
         if tuple(w.shape) != (self.nrings,):
             raise ValueError("ring_weight must have one entry per ring")
         out = torch.empty((self.nmaps, self.nalm), dtype=torch.complex128,
-                          device=self.device) if out is None else out
+                          device=self.device) if out is None else \
+            self._check_out(out, torch.complex128, self.nmaps * self.nalm, "out")
         tmp = torch.empty((self.nmaps, self.npix), dtype=torch.float64,
                           device=self.device) if niter > 0 else None
         ws = self.workspace()

@@ -3,6 +3,7 @@ rejects invalid descriptors on the host (no GPU work is issued)."""
 import ctypes
 import os
 import re
+import sys
 
 import numpy as np
 import pytest
@@ -51,7 +52,7 @@ def test_status_strings_and_version(L):
 
 
 def _desc(L, lmax=8, nrings=3, cth=None, sth=None, nphi=None, mval=None, start=None, nm=None,
-          nmaps=1, precision=0, flags=0):
+          nmaps=1, precision=0, flags=0, npix=0):
     keep = []
     cth = np.array([0.5, 0.0, -0.5]) if cth is None else np.asarray(cth, float)
     sth = np.sqrt((1 - cth) * (1 + cth)) if sth is None else np.asarray(sth, float)
@@ -77,6 +78,7 @@ def _desc(L, lmax=8, nrings=3, cth=None, sth=None, nphi=None, mval=None, start=N
     d.nmaps = nmaps
     d.precision = precision
     d.flags = flags
+    d.npix = npix
     return d, keep
 
 
@@ -98,6 +100,8 @@ def _desc(L, lmax=8, nrings=3, cth=None, sth=None, nphi=None, mval=None, start=N
     (dict(nmaps=0), "INVALID"),
     (dict(precision=7), "UNSUPPORTED"),
     (dict(flags=1 << 5), "INVALID"),
+    (dict(npix=23), "INVALID"),                                   # shorter than the rings
+    (dict(npix=-1), "INVALID"),
 ])
 def test_plan_rejects_invalid_descriptors_on_host(L, case, expect):
     lib = L.load()
@@ -119,6 +123,10 @@ def test_null_arguments(L):
     assert lib.sht_plan_workspace_size(None, ctypes.byref(n)) == L.SHT_ERR_BAD_HANDLE
     assert lib.sht_alm2map(None, None, None, None, 0, None) == L.SHT_ERR_BAD_HANDLE
     assert lib.sht_alm2map_adjoint(None, None, None, None, 0, None) == L.SHT_ERR_BAD_HANDLE
+    c = ctypes.c_int32()
+    assert lib.sht_plan_get_config(None, ctypes.byref(c)) == L.SHT_ERR_BAD_HANDLE
+    assert lib.sht_plan_set_config(None, 2) == L.SHT_ERR_BAD_HANDLE
+    assert lib.sht_plan_autotune(None, None, None, None, 0, None, None) == L.SHT_ERR_BAD_HANDLE
 
 
 def test_package_import_fails_loudly_without_library(tmp_path):
@@ -130,3 +138,16 @@ def test_package_import_fails_loudly_without_library(tmp_path):
     spec.loader.exec_module(mod)
     with pytest.raises(ImportError):
         mod.load(str(tmp_path / "missing.so"))
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """torch bundles a HIP runtime with the system's soname; importing the
+    package before torch must still leave one runtime in the process, or
+    torch's device memory and streams would be foreign to the library's."""
+    import subprocess
+    code = ("import sys; sys.path.insert(0, %r); import paper_1010_1260_amd; "
+            "maps = open('/proc/self/maps').read(); "
+            "print(len({l.split()[-1] for l in maps.splitlines() if 'libamdhip64' in l}))") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "1"
