@@ -58,9 +58,9 @@ struct PairKeyHash {
 };
 
 // Default launch shape of the FP64 forward Legendre kernel by problem size.
-// The best block shape depends on the input size (Sec. 5 finds no single
-// segment length / thread count best for every size and proposes tuning per
-// size), so the default comes from a table measured over sizes and
+// The best block shape depends on the input size (Sec. 5 proposes tuning
+// per size; Sec. 6.1 finds no single segment length / thread count best for
+// every size), so the default comes from a table measured over sizes and
 // sht_plan_autotune can refine it per plan.  Key: the waves the launch would
 // have with one ring pair per lane, per compute unit.  More pairs per lane
 // give each wave independent recurrences to interleave but fewer waves to
