@@ -1,7 +1,8 @@
 """Pins of the oracle's whole transform and of its Fourier step.
 
 * brute force: the literal double sum of Eq. (alm2mapDef) at every pixel with
-  exact-rational Legendre functions (l_max <= 16);
+  exact-rational Legendre functions (l_max <= 16), and at sampled pixels of
+  the l_max = 64, nside = 32 workload with scipy's spherical harmonics;
 * the per-ring Fourier step against the literal sum of Eq. (Delta2map) for
   rings with fewer, equal and more pixels than modes (the wrap rule of
   Sec. 2.2.2);
@@ -20,6 +21,37 @@ from oracle import brute, ref
 
 def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_l64_nside32_against_scipy_literal_sum():
+    """The l_max = 64, nside = 32 workload at every 16th pixel against the
+    literal sum over l and m = -l..l of Eq. (alm2mapDef), with
+    a_{l,-m} = (-1)^m conj(a_lm) (Sec. 2.1) and scipy's Y_lm, which carries
+    the Condon-Shortley phase the paper's mu_m (Eq. pmm) does not:
+    Y_lm(paper) = (-1)^m Y_lm(scipy) for every m of either sign."""
+    sps = pytest.importorskip("scipy.special")
+    lmax, nside = 64, 32
+    g = W.healpix_geometry(nside)
+    a = W.config_alm(1)
+    off = W.alm_offsets(lmax, W.mvals(lmax))
+    th = np.repeat(g.theta, g.nphi)
+    ph = np.concatenate([g.phi0[r] + 2 * np.pi * np.arange(g.nphi[r]) / g.nphi[r]
+                         for r in range(g.nrings)])
+    pix = np.arange(0, g.npix, 16)
+    th, ph = th[pix], ph[pix]
+    s = np.zeros(len(pix), dtype=np.complex128)
+    for ell in range(lmax + 1):
+        for mu in range(-ell, ell + 1):
+            m = abs(mu)
+            alm = a[off[m] + ell - m]
+            if m == 0:
+                alm = complex(alm.real, 0.0)
+            amu = alm if mu >= 0 else (-1) ** m * np.conj(alm)
+            s += amu * (-1) ** mu * sps.sph_harm_y(ell, mu, th, ph)
+    assert np.max(np.abs(s.imag)) < 1e-13 * np.max(np.abs(s.real))
+    e = ref.alm2map(lmax, g, a)[pix]
+    assert _rel(s.real, e) < 1e-13
+    assert np.max(np.abs(s.real - e)) < 1e-13 * np.max(np.abs(e))
 
 
 @pytest.mark.parametrize("lmax,nside", [(8, 4), (16, 8), (16, 2)])
