@@ -154,6 +154,41 @@ def run_uneven(args, torch, np, W, dev):
             "tuned_chains_waves_per_cu": list(cfg), "autotune_s": tune_s}
 
 
+def run_transfer(plan, alms_np, torch, np, reps=3):
+    """Transfer-inclusive rate of one batch: a_lm from pinned host memory to
+    the device, the transform, the maps back to pinned host memory (the
+    paper's GPU timing spans kernel launch to result retrieval, Sec. 6).
+    Reported beside the headline, never as it."""
+    dev = plan.device
+    h_alm = torch.empty((plan.nmaps, plan.nalm), dtype=torch.complex128, pin_memory=True)
+    h_alm.copy_(torch.from_numpy(np.stack(alms_np)))
+    h_map = torch.empty((plan.nmaps, plan.npix), dtype=torch.float64, pin_memory=True)
+    d_alm = torch.empty((plan.nmaps, plan.nalm), dtype=torch.complex128, device=dev)
+    d_map = torch.empty((plan.nmaps, plan.npix), dtype=torch.float64, device=dev)
+
+    def once():
+        d_alm.copy_(h_alm, non_blocking=True)
+        plan.alm2map(d_alm, out=d_map)
+        h_map.copy_(d_map, non_blocking=True)
+
+    once()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        once()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    h2d = float(h_alm.numel() * 16)
+    d2h = float(h_map.numel() * 8)
+    return {"ms_per_batch": ms, "maps_per_s": plan.nmaps / (ms * 1e-3),
+            "h2d_bytes": h2d, "d2h_bytes": d2h,
+            "host_link_GBps_if_serial": (h2d + d2h) / (ms * 1e-3) / 1e9,
+            "buffers": "pinned host (hipHostMalloc through torch), one stream, no overlap"}
+
+
 def run_grad(args, torch, np, W, dev):
     """The differentiation workload: 8 maps, l_max 1024, nside 512, loss
     0.5 ||alm2map(a) - d||^2 with d ~ N(0, 1) per pixel; one step = forward
@@ -198,6 +233,8 @@ def main() -> int:
     ap.add_argument("--nside", type=int, default=2048)
     ap.add_argument("--nmaps", type=int, default=16, help="batch of the mixed-precision run")
     ap.add_argument("--only", choices=["all", "fp32_mfma", "bf16x3_mfma", "fp64"], default="all")
+    ap.add_argument("--no-transfer", action="store_true",
+                    help="skip the transfer-inclusive (pinned host buffers) timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--uneven", action="store_true",
                     help="also time the batched uneven workload (64 maps, l_max in "
@@ -294,7 +331,7 @@ def main() -> int:
             "legendre_roofline": {"bound": "alu", "achieved": flops / (leg * 1e-3) / 1e12,
                                   "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
                                   "frac": flops / (leg * 1e-3) / PEAK_FP64,
-                                  "kernel": "k_legendre_fwd<2>",
+                                  "kernel": f"k_legendre_fwd<{fp64['plan'].config}>",
                                   "flops_per_launch": flops},
             "fourier_GBps": fft_bytes_per_map / (float(fp64["st"][2]) * 1e-3) / 1e9,
             "map2alm": fp64["map2alm"],
@@ -358,6 +395,8 @@ def main() -> int:
                                                       "maps": B}
             res["rel_err_mixed_vs_fp64_gpu"] = forms[best]["rel_err_vs_fp64_gpu"]
             del refs
+        if not args.no_transfer:
+            res["transfer_inclusive"] = run_transfer(mixed["plan"], alms_np, torch, np)
     else:
         t = fp64["wall"] / args.steps
         res.update({"value": 1.0 / t, "unit": "maps/s", "ms_per_step": t * 1e3, "dtype": "f64",
