@@ -206,13 +206,17 @@ __global__ __launch_bounds__(64) void k_legendre_fwd(
 // c_lm, so the result is bitwise reproducible.
 
 constexpr int kAdjTile = 16;
+// Row length of the reduction buffer: 64 lane partials plus one pad entry.
+// The reduction reads a column (lanes 0..15 take rows 0..15); with rows of
+// exactly 64 entries (1 KB) those reads would all fall in one LDS bank.
+constexpr int kAdjRow = 65;
 
 template <int CH>
 __device__ inline void adj_one_m(const Chains<CH> &g, const double (&s)[CH], int m, int i,
                                  long long off, double mum, int lmax,
                                  const double *__restrict__ A,
                                  const double2 *__restrict__ dt, long long dtbase, int nrings,
-                                 double2 *__restrict__ part, double2 (*red)[64])
+                                 double2 *__restrict__ part, double2 (*red)[kAdjRow])
 {
     const int len = lmax - m + 1;
     const int lane = threadIdx.x;
@@ -301,7 +305,7 @@ __global__ __launch_bounds__(64) void k_legendre_adj(
     const double *__restrict__ A, const double2 *__restrict__ dt, int nrings,
     double2 *__restrict__ part, long long nalm, long long total)
 {
-    __shared__ double2 red[kAdjTile][64];
+    __shared__ double2 red[kAdjTile][kAdjRow];
     const long long L = xcd_logical(blockIdx.x, total);
     const int pb = (int)(L % pblocks);
     const long long rest = L / pblocks;
