@@ -72,7 +72,7 @@ def run_plan(plan, alm, steps, warmup, lib, hip, torch, np):
     """Time `steps` transforms after `warmup`; returns wall seconds, stage ms, output."""
     dev = plan.device
     out = torch.empty((plan.nmaps, plan.npix), dtype=torch.float64, device=dev)
-    ws = plan.workspace()
+    ws = plan.workspace(full=False)
     sh = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     nev = 4
     evs = []

@@ -124,6 +124,8 @@ typedef struct {
     size_t workspace_bytes;   /* for sht_alm2map / sht_alm2map_adjoint              */
     size_t delta_bytes;       /* nmaps * nrings * nm * 16                          */
     size_t table_bytes;       /* device memory held by the plan                     */
+    size_t forward_workspace_bytes; /* enough for sht_alm2map, sht_alm2map_events and
+                                       sht_plan_autotune (no adjoint partial sums)  */
 } sht_plan_info;
 
 /* Build a plan: validate the descriptor, pair mirror rings, precompute the
@@ -142,7 +144,9 @@ sht_status sht_plan_destroy(sht_plan_t plan);
 
 sht_status sht_plan_get_info(sht_plan_t plan, sht_plan_info *info);
 
-/* Bytes of device workspace sht_alm2map and sht_alm2map_adjoint need. */
+/* Bytes of device workspace every call of the plan can use (the largest
+ * need: sht_alm2map_adjoint and sht_map2alm).  Synthesis alone needs only
+ * sht_plan_info.forward_workspace_bytes. */
 sht_status sht_plan_workspace_size(sht_plan_t plan, size_t *bytes);
 
 /* Launch shape of an FP64 plan's forward Legendre kernel: chains = ring
@@ -169,7 +173,7 @@ sht_status sht_plan_autotune(sht_plan_t plan, const double *alm, double *map, vo
 /* alm2map (Eq. alm2mapDef): alm device complex128 [nmaps][nalm] (read),
  * map device float64 [nmaps][npix] (written at every ring pixel; pixels not
  * covered by any ring are left untouched), ws device scratch of at least
- * sht_plan_workspace_size bytes (contents on entry ignored). */
+ * sht_plan_info.forward_workspace_bytes (contents on entry ignored). */
 sht_status sht_alm2map(sht_plan_t plan, const double *alm, double *map,
                        void *ws, size_t ws_bytes, void *stream);
 

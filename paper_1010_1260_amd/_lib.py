@@ -71,6 +71,7 @@ class PlanInfo(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t),
         ("delta_bytes", ctypes.c_size_t),
         ("table_bytes", ctypes.c_size_t),
+        ("forward_workspace_bytes", ctypes.c_size_t),
     ]
 
 

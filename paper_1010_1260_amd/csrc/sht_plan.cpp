@@ -539,9 +539,16 @@ sht_status sht_plan_destroy(sht_plan_t p)
     return SHT_OK;
 }
 
+// Synthesis needs the prescaled coefficients and Delta; the adjoint needs
+// Delta~ and the per-ring-block partial sums, which dominate for many maps.
+static size_t fwd_workspace_bytes(const sht_plan_s *p)
+{
+    return p->ws_ap_bytes + p->ws_delta_bytes;
+}
+
 static size_t workspace_bytes(const sht_plan_s *p)
 {
-    const size_t fwd = p->ws_ap_bytes + p->ws_delta_bytes;
+    const size_t fwd = fwd_workspace_bytes(p);
     const size_t adj = p->ws_delta_bytes + align_up(sht::adj_part_bytes(p), 256);
     return std::max(fwd, adj);
 }
@@ -567,6 +574,7 @@ sht_status sht_plan_get_info(sht_plan_t p, sht_plan_info *info)
     info->mmax = p->mmax;
     info->nmaps = p->nmaps;
     info->workspace_bytes = workspace_bytes(p);
+    info->forward_workspace_bytes = fwd_workspace_bytes(p);
     info->delta_bytes = (size_t)p->nmaps * (size_t)p->nrings * (size_t)p->nm * sizeof(double2);
     info->table_bytes = p->table_bytes;
     return SHT_OK;
@@ -596,7 +604,7 @@ sht_status sht_alm2map(sht_plan_t p, const double *alm, double *map, void *ws, s
     sht_status s = check_plan(p);
     if (s != SHT_OK) return s;
     if (!alm || !map) return SHT_ERR_INVALID_ARG;
-    if (!ws || ws_bytes < workspace_bytes(p)) return SHT_ERR_WORKSPACE;
+    if (!ws || ws_bytes < fwd_workspace_bytes(p)) return SHT_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     double2 *delta = (double2 *)((char *)ws + p->ws_ap_bytes);
     s = legendre_stage(p, alm, ws, delta, st, nullptr);
@@ -631,7 +639,7 @@ sht_status sht_plan_autotune(sht_plan_t p, const double *alm, double *map, void 
     sht_status s = check_plan(p);
     if (s != SHT_OK) return s;
     if (!alm || !map) return SHT_ERR_INVALID_ARG;
-    if (!ws || ws_bytes < workspace_bytes(p)) return SHT_ERR_WORKSPACE;
+    if (!ws || ws_bytes < fwd_workspace_bytes(p)) return SHT_ERR_WORKSPACE;
     if (p->precision != SHT_FP64) return SHT_OK;   // nothing to tune
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) return SHT_ERR_HIP;
@@ -693,7 +701,7 @@ sht_status sht_alm2map_events(sht_plan_t p, const double *alm, double *map, void
     if (!alm || !map || !events) return SHT_ERR_INVALID_ARG;
     for (int k = 0; k < 4; ++k)
         if (!events[k]) return SHT_ERR_INVALID_ARG;
-    if (!ws || ws_bytes < workspace_bytes(p)) return SHT_ERR_WORKSPACE;
+    if (!ws || ws_bytes < fwd_workspace_bytes(p)) return SHT_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     double2 *delta = (double2 *)((char *)ws + p->ws_ap_bytes);
     s = from_hip(hipEventRecord((hipEvent_t)events[0], st));

@@ -100,10 +100,14 @@ class Plan:
     def workspace_bytes(self) -> int:
         return int(self.info.workspace_bytes)
 
-    def workspace(self) -> torch.Tensor:
-        if self._ws is None:
-            self._ws = torch.empty(max(1, self.workspace_bytes), dtype=torch.uint8,
-                                   device=self.device)
+    def workspace(self, full: bool = True) -> torch.Tensor:
+        """Device scratch for the plan's calls: synthesis needs only the
+        forward part (full=False); the adjoint and map2alm need all of it.
+        Held by the plan and grown on the first call that needs more."""
+        need = max(1, self.workspace_bytes if full else int(self.info.forward_workspace_bytes))
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         return self._ws
 
     @property
@@ -122,7 +126,7 @@ class Plan:
         a = self._alm_in(alm)
         out = self._new_map() if out is None else \
             self._check_out(out, torch.float64, self.nmaps * self.npix, "out")
-        ws = self.workspace()
+        ws = self.workspace(full=False)
         cp = cache_path.encode() if cache_path else None
         L.check(L.load().sht_plan_autotune(self._h, _ptr(a), _ptr(out), _ptr(ws), ws.numel(),
                                            cp, ctypes.c_void_p(_cur_stream(self.device))),
@@ -167,7 +171,7 @@ class Plan:
         a = self._alm_in(alm)
         out = self._new_map() if out is None else \
             self._check_out(out, torch.float64, self.nmaps * self.npix, "out")
-        ws = self.workspace()
+        ws = self.workspace(full=False)
         L.check(L.load().sht_alm2map(self._h, _ptr(a), _ptr(out), _ptr(ws), ws.numel(),
                                      ctypes.c_void_p(_cur_stream(self.device))), "sht_alm2map")
         return out
@@ -208,7 +212,7 @@ class Plan:
         a = self._alm_in(alm)
         out = torch.empty((self.nmaps, self.nm, self.nrings), dtype=torch.complex128,
                           device=self.device)
-        ws = self.workspace()
+        ws = self.workspace(full=False)
         L.check(L.load().sht_alm2delta(self._h, _ptr(a), _ptr(out), _ptr(ws), ws.numel(),
                                        ctypes.c_void_p(_cur_stream(self.device))),
                 "sht_alm2delta")

@@ -119,3 +119,35 @@ def test_stale_error_of_the_caller_is_not_reported(P):
     assert hip.hipSetDevice(ctypes.c_int(9999)) != 0
     plan.alm2map(a)
     torch.cuda.synchronize()
+
+
+def test_forward_workspace_suffices_for_synthesis(P):
+    """Synthesis runs in forward_workspace_bytes; the adjoint, which also
+    keeps partial sums per block of 256 ring pairs, asks for more once there
+    are several blocks (320 ring pairs at nside 160: two)."""
+    import ctypes
+    from paper_1010_1260_amd import _lib as L
+    _say("forward-only workspace")
+    lmax, nside, nmaps = 128, 160, 3
+    g = W.healpix_geometry(nside)
+    plan = P.Plan(lmax, g, nmaps=nmaps)
+    fwd = int(plan.info.forward_workspace_bytes)
+    assert 0 < fwd < plan.workspace_bytes
+    alms = np.stack([W.random_alm(lmax, [604, i]) for i in range(nmaps)])
+    a = torch.from_numpy(alms).to(_dev())
+    ws = torch.empty(fwd, dtype=torch.uint8, device=_dev())
+    out = torch.empty((nmaps, plan.npix), dtype=torch.float64, device=_dev())
+    lib = L.load()
+    st = ctypes.c_void_p(torch.cuda.current_stream(_dev()).cuda_stream)
+    vp = ctypes.c_void_p
+    assert lib.sht_alm2map(plan.handle, vp(a.data_ptr()), vp(out.data_ptr()), vp(ws.data_ptr()),
+                           fwd, st) == L.SHT_OK
+    assert lib.sht_alm2map(plan.handle, vp(a.data_ptr()), vp(out.data_ptr()), vp(ws.data_ptr()),
+                           fwd - 1, st) == L.SHT_ERR_WORKSPACE
+    adj = torch.empty((nmaps, plan.nalm), dtype=torch.complex128, device=_dev())
+    assert lib.sht_alm2map_adjoint(plan.handle, vp(out.data_ptr()), vp(adj.data_ptr()),
+                                   vp(ws.data_ptr()), fwd, st) == L.SHT_ERR_WORKSPACE
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for i in range(nmaps):
+        assert _rel(got[i], ref.alm2map(lmax, g, alms[i])) < 1e-12
