@@ -4,8 +4,9 @@ mixed precision against FP64.
 
 Workloads (seeded Gaussian a_lm, C_l = 1/(l(l+1)), HEALPix rings,
 50,331,648 pixels, 8191 rings; inputs resident in HBM before timing):
-  * mixed: a batch of 16 maps; FP64 recurrence, FP32 matrix-core contraction,
-    FP64 ring Fourier synthesis -- the headline value;
+  * mixed: a batch of 16 maps; FP64 recurrence, matrix-core contraction in
+    each mixed form (FP32, 3-way split BF16, 2-way split FP16), FP64 ring
+    Fourier synthesis -- the headline value is the fastest form;
   * fp64:  one map at a time, everything FP64 -- the comparison.
 One step is the whole transform of one batch through the C ABI (coefficient
 prescale, Legendre stage, per-ring Fourier synthesis).  Stage durations come
@@ -29,6 +30,14 @@ METRIC = "maps/s at ℓmax=4096,nside=2048: mixed-precision vs FP64, rel err≤1
 PEAK_FP64 = 78.6e12    # MI355X FP64 vector FLOP/s
 PEAK_FP32_MFMA = 157.3e12
 PEAK_BF16_MFMA = 2.5e15   # dense
+PEAK_F16_MFMA = 2.5e15    # dense
+# mixed forms: matrix-core peak of the operand type, kernel, matrix-core
+# products per useful product, dtype label
+FORMS = {
+    "fp32_mfma": (PEAK_FP32_MFMA, "k_legendre_mfma_f32", 1, "f32"),
+    "bf16x3_mfma": (PEAK_BF16_MFMA, "k_legendre_mfma_bf16x3", 6, "bf16x3"),
+    "f16x2_mfma": (PEAK_F16_MFMA, "k_legendre_mfma_f16x2", 3, "f16x2"),
+}
 PEAK_HBM = 8.0e12      # bytes/s
 
 
@@ -232,7 +241,7 @@ def main() -> int:
     ap.add_argument("--lmax", type=int, default=4096)
     ap.add_argument("--nside", type=int, default=2048)
     ap.add_argument("--nmaps", type=int, default=16, help="batch of the mixed-precision run")
-    ap.add_argument("--only", choices=["all", "fp32_mfma", "bf16x3_mfma", "fp64"], default="all")
+    ap.add_argument("--only", choices=["all", "fp64", *FORMS], default="all")
     ap.add_argument("--no-transfer", action="store_true",
                     help="skip the transfer-inclusive (pinned host buffers) timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -277,7 +286,7 @@ def main() -> int:
 
     mixed_runs = {}
     fp64 = None
-    for prec in ("fp32_mfma", "bf16x3_mfma"):
+    for prec in FORMS:
         if args.only in ("all", prec):
             plan = Plan(Lmax, geom, nmaps=B, precision=prec, device=dev)
             alm = torch.from_numpy(np.stack(alms_np)).to(dev)
@@ -346,9 +355,8 @@ def main() -> int:
             # accumulate of a real P_lm); the FP64 recurrence (4 per (pair, l, m))
             # runs on the vector units beside it
             flops = float(npairs) * float(nalm) * 4.0 * B
-            peak = PEAK_FP32_MFMA if prec == "fp32_mfma" else PEAK_BF16_MFMA
-            kern = "k_legendre_mfma_f32" if prec == "fp32_mfma" else "k_legendre_mfma_bf16x3"
-            executed = flops * (1 if prec == "fp32_mfma" else 6)
+            peak, kern, nprod, _ = FORMS[prec]
+            executed = flops * nprod
             traffic = recorded_traffic(f"{kern}|lmax={Lmax}|nside={N}|nmaps={B}")
             forms[prec] = {
                 "maps_per_s": B / t, "ms_per_step": t * 1e3,
@@ -366,8 +374,7 @@ def main() -> int:
         fb = forms[best]
         res.update({
             "value": B / t, "unit": "maps/s", "ms_per_step": t * 1e3,
-            "dtype": ("f32" if best == "fp32_mfma" else "bf16x3") +
-                     " matrix-core contraction + f64 recurrence and FFT",
+            "dtype": FORMS[best][3] + " matrix-core contraction + f64 recurrence and FFT",
             "config": {"workload": f"alm2map mixed precision, batch of {B} maps, lmax={Lmax}, "
                                    f"HEALPix nside={N}", "lmax": Lmax, "nside": N,
                        "nmaps": B, "precision": best, "npix": geom.npix,

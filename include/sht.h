@@ -73,9 +73,18 @@ typedef enum {
                           rounded to FP32) and two-level FP32 accumulation.  The ring
                           Fourier step and the adjoint stay FP64.  Relative L2 error of
                           a map against FP64 about 1e-7.                                  */
-    SHT_BF16X3_MFMA = 2 /* as SHT_FP32_MFMA, with every FP32 operand split into three BF16
+    SHT_BF16X3_MFMA = 2, /* as SHT_FP32_MFMA, with every FP32 operand split into three BF16
                            parts (8+8+8 bits) and six BF16 matrix-core products per
                            tile; same accuracy class, higher matrix-core rate.          */
+    SHT_F16X2_MFMA = 3  /* as SHT_FP32_MFMA, with every FP32 operand split into two FP16
+                           parts (11+11 bits) and three FP16 matrix-core products per
+                           tile (the dropped low x low term is below 2^-21 relative);
+                           both operands are scaled by powers of two into FP16's range
+                           (the coefficients per map and 128-row block of l), so the
+                           accuracy class is that of the FP32 form.  Fewest matrix-core
+                           and vector instructions of the mixed forms.
+                           All mixed forms hold a_lm P_lm sums in FP32: coefficients
+                           must stay within FP32 range (|a_lm| below about 1e30).    */
 } sht_precision;
 
 #define SHT_MAX_LMAX 16383
@@ -241,6 +250,11 @@ sht_status sht_delta2alm_adjoint(sht_plan_t plan, const double *delta, double *a
  * counter; the counter only distributes work, so results are identical to
  * the single-plan transforms and independent of the launch shape.  The
  * per-ring Fourier step runs as one launch per ring size class.
+ *
+ * Streams: the work counter lives in the caller's workspace (its first 256
+ * bytes), so transforms of one batch on different streams are safe when
+ * they use distinct workspaces, as for plans.  A captured graph keeps the
+ * workspace it was captured with: replays of one graph must not overlap.
  * ------------------------------------------------------------------------- */
 typedef struct sht_batch_s *sht_batch_t;
 

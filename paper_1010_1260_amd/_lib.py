@@ -23,6 +23,7 @@ SHT_ERR_WORKSPACE = -6
 SHT_FP64 = 0
 SHT_FP32_MFMA = 1
 SHT_BF16X3_MFMA = 2
+SHT_F16X2_MFMA = 3
 SHT_FLAG_NO_PAIRING = 1
 
 SHT_MAX_LMAX = 16383

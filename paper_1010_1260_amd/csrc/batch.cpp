@@ -27,6 +27,11 @@ const int kWaveChoices[] = {4, 8, 16};  // persistent waves per CU
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// The workspace starts with the persistent launch's work counter (reset by
+// a kernel at the start of every transform), so that transforms of one
+// batch with distinct workspaces share no device state.
+constexpr size_t kCounterBytes = 256;
+
 }  // namespace
 
 struct sht_batch_s {
@@ -39,7 +44,6 @@ struct sht_batch_s {
     BatchTile *d_tiles[3];           // work lists for 1, 2, 4 chains per lane
     int ntiles[3];
     BatchClass cls[sht::kNumRingClasses];
-    int *d_counter;
     long long max_nalm;
     size_t ws_bytes;
     int chains;                      // launch shape in use
@@ -70,7 +74,6 @@ void free_batch(sht_batch_s *b)
         if (b->d_tiles[i]) (void)hipFree(b->d_tiles[i]);
     for (int c = 0; c < sht::kNumRingClasses; ++c)
         if (b->cls[c].d_items) (void)hipFree(b->cls[c].d_items);
-    if (b->d_counter) (void)hipFree(b->d_counter);
     if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
 }
@@ -81,7 +84,7 @@ sht_status enqueue(sht_batch_t b, const double *const *alms, double *const *maps
     const int ci = chain_index(b->chains);
     hipError_t e = sht::launch_batch_legendre(
         b->d_maps, b->n, b->max_nalm, b->d_tiles[ci], b->ntiles[ci], b->chains,
-        b->waves_per_cu * b->num_cus, alms, ws, b->d_counter, st);
+        b->waves_per_cu * b->num_cus, alms, ws, static_cast<int *>(ws), st);
     if (e == hipSuccess) e = sht::launch_ring_synth_batch(b->cls, b->d_maps, maps, ws, st);
     return e == hipSuccess ? SHT_OK : SHT_ERR_HIP;
 }
@@ -118,9 +121,9 @@ sht_status sht_plan_batch(sht_batch_t *out, const sht_plan_t *plans, int32_t n)
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) { delete b; return SHT_ERR_HIP; }
     b->num_cus = prop.multiProcessorCount;
 
-    // per-map descriptors and workspace layout
+    // per-map descriptors and workspace layout (after the work counter)
     std::vector<BatchMap> maps(n);
-    size_t off = 0;
+    size_t off = kCounterBytes;
     std::ostringstream sig;
     sig << prop.gcnArchName << "|n=" << n;
     b->max_nalm = 0;
@@ -191,9 +194,7 @@ sht_status sht_plan_batch(sht_batch_t *out, const sht_plan_t *plans, int32_t n)
     if (st == SHT_OK &&
         (hipMalloc((void **)&b->d_maps, maps.size() * sizeof(BatchMap)) != hipSuccess ||
          hipMemcpy(b->d_maps, maps.data(), maps.size() * sizeof(BatchMap),
-                   hipMemcpyHostToDevice) != hipSuccess ||
-         hipMalloc((void **)&b->d_counter, sizeof(int)) != hipSuccess ||
-         hipMemset(b->d_counter, 0, sizeof(int)) != hipSuccess))
+                   hipMemcpyHostToDevice) != hipSuccess))
         st = SHT_ERR_OOM;
     if (st != SHT_OK) {
         free_batch(b);

@@ -14,13 +14,18 @@
 // Analysis (adjoint): G_k = sum_j g_j e^{-2 pi i j k / n} by the reverse
 // construction, then Dt_m = c_m e^{-i m phi0} G_{m mod n} (c_0 = 1, c_m = 2).
 //
-// One workgroup (512 threads) per ring and map; the whole ring lives in LDS.
-// DFTs of 7-smooth length run as a Stockham auto-sort FFT (radices 8, 4, 2, 3,
-// 5, 7 and 8; every pass loads its butterfly inputs into registers, barriers, and
-// stores in place, so one LDS buffer suffices).  Other lengths use
-// Bluestein's chirp-z algorithm with a power-of-two convolution whose
-// kernel spectrum is precomputed at plan time.  Twiddles come from
-// per-length tables computed on the host in extended precision.
+// One workgroup per ring and map; the whole ring lives in LDS.  Rings are
+// grouped by FFT length into three size classes (up to 2048, 4096 and 8192
+// points) run by 256-, 512- and 1024-thread workgroups, each with an LDS
+// layout computed on the host for the class.  DFTs of 7-smooth length run as
+// a Stockham auto-sort FFT (radices 8, 4, 2, 3, 5 and 7; every pass loads its
+// butterfly inputs into registers, barriers, and stores in place, so one LDS
+// buffer suffices).  Other lengths use Bluestein's chirp-z algorithm with a
+// 7-smooth convolution length whose kernel spectrum is precomputed at plan
+// time; an even length whose half is not 7-smooth is split into the DFTs of
+// its even- and odd-indexed inputs (two Bluestein transforms of half length)
+// joined by one radix-2 step.  Twiddles come from per-length tables computed
+// on the host in extended precision.
 #include "sht_internal.h"
 
 // Every fused multiply-add in this file is written out (fma, cmul): no

@@ -136,6 +136,10 @@ struct sht_plan_s {
     long long *d_boff16; // [nm] first 16-row block of each m (FP32 matrix-core operand packing)
     int32_t *d_bm16;     // [nblk16] index of the m that owns each 16-row block
     long long nblk16;    // 16-row blocks over all m
+    long long *d_soff;   // [nm] first 128-row super-block of each m (split-FP16 operand packing)
+    int32_t *d_sbm;      // [nsuper] index of the m that owns each super-block
+    double *d_Asb;       // [nsuper][128] d_A per super-block, zero past each m's last row
+    long long nsuper;    // 128-row super-blocks over all m
     sht::RingDesc *d_rings;
     double2 *d_pool;     // twiddle and Bluestein tables
     size_t table_bytes;
@@ -177,6 +181,12 @@ hipError_t launch_prescale_bf16x3(const sht_plan_s *p, const double *alm, void *
                                   hipStream_t st);
 hipError_t launch_legendre_mfma_bf16x3(const sht_plan_s *p, const void *Bb, double2 *delta,
                                        hipStream_t st);
+size_t f16_bytes(const sht_plan_s *p);
+int f16_super_rows();
+hipError_t launch_prescale_f16x2(const sht_plan_s *p, const double *alm, void *Bb,
+                                 hipStream_t st);
+hipError_t launch_legendre_mfma_f16x2(const sht_plan_s *p, const void *Bb, double2 *delta,
+                                      hipStream_t st);
 hipError_t launch_ring_synth(const sht_plan_s *p, const double2 *delta, double *map,
                              hipStream_t st);
 hipError_t launch_ring_anal(const sht_plan_s *p, const double *map, double2 *dt, hipStream_t st,

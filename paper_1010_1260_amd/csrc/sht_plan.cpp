@@ -106,7 +106,7 @@ void free_tables(sht_plan_s *p)
 {
     void *ptrs[] = {p->d_pairs, p->d_mval, p->d_moff, p->d_mu, p->d_A, p->d_cn,
                     p->d_minv, p->d_rings, p->d_pool, p->d_boff, p->d_boff16, p->d_bm16,
-                    p->d_bm32};
+                    p->d_bm32, p->d_soff, p->d_sbm, p->d_Asb};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (int c = 0; c < sht::kNumRingClasses; ++c) {
@@ -116,7 +116,7 @@ void free_tables(sht_plan_s *p)
     p->d_pairs = nullptr; p->d_mval = nullptr; p->d_moff = nullptr; p->d_mu = nullptr;
     p->d_A = nullptr; p->d_cn = nullptr; p->d_minv = nullptr; p->d_rings = nullptr;
     p->d_pool = nullptr; p->d_boff = nullptr; p->d_boff16 = nullptr; p->d_bm16 = nullptr;
-    p->d_bm32 = nullptr;
+    p->d_bm32 = nullptr; p->d_soff = nullptr; p->d_sbm = nullptr; p->d_Asb = nullptr;
 }
 
 sht_status check_plan(sht_plan_t p)
@@ -232,6 +232,10 @@ static sht_status legendre_stage(sht_plan_t p, const double *alm, void *ws, doub
         e = sht::launch_prescale_bf16x3(p, alm, ws, st);
         if (e == hipSuccess && ev_mid) e = hipEventRecord(ev_mid, st);
         if (e == hipSuccess) e = sht::launch_legendre_mfma_bf16x3(p, ws, delta, st);
+    } else if (p->precision == SHT_F16X2_MFMA) {
+        e = sht::launch_prescale_f16x2(p, alm, ws, st);
+        if (e == hipSuccess && ev_mid) e = hipEventRecord(ev_mid, st);
+        if (e == hipSuccess) e = sht::launch_legendre_mfma_f16x2(p, ws, delta, st);
     } else {
         e = sht::launch_prescale(p, alm, (double2 *)ws, st);
         if (e == hipSuccess && ev_mid) e = hipEventRecord(ev_mid, st);
@@ -270,7 +274,7 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     if (!d->cth || !d->sth || !d->phi0 || !d->nphi) return SHT_ERR_INVALID_ARG;
     if (d->flags & ~SHT_FLAG_NO_PAIRING) return SHT_ERR_INVALID_ARG;
     if (d->precision != SHT_FP64 && d->precision != SHT_FP32_MFMA &&
-        d->precision != SHT_BF16X3_MFMA)
+        d->precision != SHT_BF16X3_MFMA && d->precision != SHT_F16X2_MFMA)
         return SHT_ERR_UNSUPPORTED;
     sht::clear_stale_error();
     std::vector<int32_t> mval(d->nm);
@@ -483,6 +487,31 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
             st = upload(&p->d_bm16, bm16, &tb);
         }
     }
+    if (st == SHT_OK && p->precision == SHT_F16X2_MFMA) {
+        // split-FP16 form: super-blocks of 128 rows per m, and the
+        // recurrence coefficients copied per super-block with zeros past each
+        // m's last row
+        const int SR = sht::f16_super_rows();
+        std::vector<long long> soff(d->nm);
+        long long acc_s = 0;
+        for (int i = 0; i < d->nm; ++i) {
+            soff[i] = acc_s;
+            acc_s += (d->lmax - mval[i] + 1 + SR - 1) / SR;
+        }
+        p->nsuper = acc_s;
+        std::vector<int32_t> sbm((size_t)acc_s);
+        std::vector<double> Asb((size_t)acc_s * SR, 0.0);
+        for (int i = 0; i < d->nm; ++i) {
+            const long long e = (i + 1 < d->nm) ? soff[i + 1] : acc_s;
+            for (long long b = soff[i]; b < e; ++b) sbm[(size_t)b] = i;
+            const int len = d->lmax - mval[i] + 1;
+            for (int j = 0; j < len; ++j)
+                Asb[(size_t)soff[i] * SR + j] = A[(size_t)p->moff[i] + j];
+        }
+        st = upload(&p->d_soff, soff, &tb);
+        if (st == SHT_OK) st = upload(&p->d_sbm, sbm, &tb);
+        if (st == SHT_OK) st = upload(&p->d_Asb, Asb, &tb);
+    }
     if (st == SHT_OK) st = upload(&p->d_rings, rings, &tb);
     if (st == SHT_OK) st = upload(&p->d_pool, pb.pool, &tb);
     for (int c = 0; c < sht::kNumRingClasses && st == SHT_OK; ++c) {
@@ -521,6 +550,7 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     p->ws_ap_bytes = align_up(
         p->precision == SHT_FP32_MFMA     ? sht::mfma_bf_bytes(p)
         : p->precision == SHT_BF16X3_MFMA ? sht::bf16_bytes(p)
+        : p->precision == SHT_F16X2_MFMA  ? sht::f16_bytes(p)
                                           : (size_t)p->nmaps * (size_t)p->nalm * sizeof(double2),
         256);
     p->ws_delta_bytes = align_up((size_t)p->nmaps * (size_t)R * (size_t)p->nm * sizeof(double2), 256);

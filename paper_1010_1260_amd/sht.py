@@ -21,6 +21,21 @@ def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _stream_workspace(cache: dict, dev: torch.device, nbytes: int) -> torch.Tensor:
+    """The workspace of at least `nbytes` kept in `cache` for the current
+    stream of `dev`, allocated on that stream (torch's caching allocator
+    then only hands its memory out again in that stream's order)."""
+    need = max(1, int(nbytes))
+    key = _cur_stream(dev)
+    ws = cache.get(key)
+    if ws is None or ws.numel() < need:
+        cache.pop(key, None)
+        with torch.cuda.device(dev):
+            ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        cache[key] = ws
+    return ws
+
+
 class Plan:
     """A transform plan for one ring geometry, band limit and m-set.
 
@@ -29,7 +44,7 @@ class Plan:
     ``device`` (default: the current CUDA/HIP device).
     """
 
-    PRECISIONS = {"fp64": 0, "fp32_mfma": 1, "bf16x3_mfma": 2}
+    PRECISIONS = {"fp64": 0, "fp32_mfma": 1, "bf16x3_mfma": 2, "f16x2_mfma": 3}
 
     def __init__(self, lmax: int, geom, mval=None, nmaps: int = 1, pairing: bool = True,
                  device=None, precision: str = "fp64"):
@@ -78,7 +93,7 @@ class Plan:
         self.npairs = int(info.npairs)
         covered = int(np.sum(self._nphi))
         self._full_cover = covered == self.npix
-        self._ws = None
+        self._ws = {}
 
     # ----------------------------------------------------------------- misc
     def close(self):
@@ -101,14 +116,16 @@ class Plan:
         return int(self.info.workspace_bytes)
 
     def workspace(self, full: bool = True) -> torch.Tensor:
-        """Device scratch for the plan's calls: synthesis needs only the
-        forward part (full=False); the adjoint and map2alm need all of it.
-        Held by the plan and grown on the first call that needs more."""
-        need = max(1, self.workspace_bytes if full else int(self.info.forward_workspace_bytes))
-        if self._ws is None or self._ws.numel() < need:
-            self._ws = None
-            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
-        return self._ws
+        """Device scratch for the plan's calls on the current stream:
+        synthesis needs only the forward part (full=False); the adjoint and
+        map2alm need all of it.  The plan keeps one workspace per stream,
+        allocated on that stream and grown on the first call that needs more,
+        so calls on different streams never share one (the library's rule for
+        concurrent calls), and memory dropped when a workspace grows is only
+        reused by work ordered after the calls that used it."""
+        return _stream_workspace(self._ws, self.device,
+                                 self.workspace_bytes if full
+                                 else int(self.info.forward_workspace_bytes))
 
     @property
     def config(self) -> int:
@@ -297,7 +314,7 @@ class Batch:
         n = ctypes.c_size_t()
         L.check(lib.sht_batch_workspace_size(h, ctypes.byref(n)), "sht_batch_workspace_size")
         self.workspace_bytes = int(n.value)
-        self._ws = None
+        self._ws = {}
         self._keep = None
 
     def close(self):
@@ -312,10 +329,9 @@ class Batch:
             pass
 
     def workspace(self) -> torch.Tensor:
-        if self._ws is None:
-            self._ws = torch.empty(max(1, self.workspace_bytes), dtype=torch.uint8,
-                                   device=self.device)
-        return self._ws
+        """The batch workspace for the current stream (one per stream, so
+        that batched transforms on different streams never share one)."""
+        return _stream_workspace(self._ws, self.device, self.workspace_bytes)
 
     def new_maps(self):
         return [p._new_map().reshape(-1) for p in self.plans]
@@ -364,9 +380,11 @@ class Batch:
 
     def capture(self, alms, outs, stream: torch.cuda.Stream):
         """Capture one batched transform into a HIP graph on `stream`."""
-        pa, po = self._ptrs(alms, outs)
-        ws = self.workspace()
-        self._keep = (pa, po, list(alms), list(outs))
+        with torch.cuda.stream(stream):
+            pa, po = self._ptrs(alms, outs)
+            ws = self.workspace()
+        # the graph replays with these buffers: keep them alive with it
+        self._keep = (pa, po, ws, list(alms), list(outs))
         L.check(L.load().sht_batch_graph_capture(self._h, _ptr(pa), _ptr(po), _ptr(ws),
                                                  ws.numel(), ctypes.c_void_p(stream.cuda_stream)),
                 "sht_batch_graph_capture")

@@ -148,3 +148,34 @@ def test_batch_uneven_64_maps(P):
         num += float(np.sum((got[s0:s0 + n] - e) ** 2))
         den += float(np.sum(e ** 2))
     assert np.sqrt(num / den) < 1e-12
+
+
+def test_batch_two_streams_distinct_workspaces(P):
+    """Transforms of one batch enqueued on two streams at once, each with the
+    workspace the binding keeps for its stream: the persistent kernel's work
+    counter lives in the workspace, so the launches hand out their own tiles
+    and both equal the single-plan maps bitwise."""
+    _say("one batch on two streams with distinct workspaces")
+    lmaxes = [256, 128, 512, 64, 256, 96, 384, 128]
+    plans, alms, singles = _setup(P, lmaxes, 604)
+    b = P.Batch(plans)
+    b.set_config(1, 2)   # few persistent waves: each launch runs long enough to overlap
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s1):
+        ws1 = b.workspace()
+    with torch.cuda.stream(s2):
+        ws2 = b.workspace()
+    assert ws1.data_ptr() != ws2.data_ptr()
+    res = []
+    for rep in range(3):
+        with torch.cuda.stream(s1):
+            o1 = b.alm2map(alms)
+        with torch.cuda.stream(s2):
+            o2 = b.alm2map(alms)
+        res.append((o1, o2))
+    torch.cuda.synchronize()
+    for rep, (o1, o2) in enumerate(res):
+        for i in range(len(plans)):
+            assert torch.equal(o1[i], singles[i]), (rep, 1, i)
+            assert torch.equal(o2[i], singles[i]), (rep, 2, i)

@@ -105,7 +105,7 @@ def test_map2alm_mixed_plan_refinement(P):
     g = W.healpix_geometry(nside)
     maps = np.stack([W.random_map(g.npix, [55, b]) for b in range(3)])
     w = np.full(g.nrings, 4.0 * np.pi / g.npix)
-    for prec in ("fp32_mfma", "bf16x3_mfma"):
+    for prec in ("fp32_mfma", "bf16x3_mfma", "f16x2_mfma"):
         plan = P.Plan(lmax, g, nmaps=3, precision=prec)
         got = plan.map2alm(_to_dev(maps), w, niter=2).cpu().numpy()
         for b in range(3):

@@ -1,5 +1,6 @@
 """GPU parity of the mixed-precision batched Legendre stage (FP64 recurrence,
-FP32 or 3-way split BF16 matrix-core contraction) against the FP64 oracle.  Bound: relative L2
+FP32, 3-way split BF16 or 2-way split FP16 matrix-core contraction) against
+the FP64 oracle.  Bound: relative L2
 error <= 1e-6 per map (the target for the mixed forms); the emulated error of
 the two-level FP32 accumulation is about 1e-7."""
 import sys
@@ -37,7 +38,7 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-PRECS = ["fp32_mfma", "bf16x3_mfma"]
+PRECS = ["fp32_mfma", "bf16x3_mfma", "f16x2_mfma"]
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -106,3 +107,30 @@ def test_mixed_l4096_nside2048_x16_sampled(P, prec):
             num += float(np.sum((out[i, s0:s0 + n] - e) ** 2))
             den += float(np.sum(e ** 2))
         assert np.sqrt(num / den) < TOL, i
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixed_coefficient_range(P, prec):
+    """Coefficients spread over many binades: whole maps scaled by 1e-25 and
+    1e25 (inside the FP32 range the mixed forms accumulate in), and one map
+    whose m-blocks differ by up to 1e30.  The split-FP16 form rescales per
+    map and 128-row block of l, so its error stays that of the FP32 form."""
+    _say("mixed coefficient range", prec)
+    lmax, nside = 300, 96
+    g = W.healpix_geometry(nside)
+    mv = np.arange(lmax + 1)
+    off = W.alm_offsets(lmax, mv)
+    base = [W.random_alm(lmax, [305, i]) for i in range(4)]
+    wild = base[3].copy()
+    for m in range(lmax + 1):
+        wild[off[m]:off[m] + lmax - m + 1] *= 10.0 ** (30 * ((m % 7) / 6.0) - 15)
+    # l-dependent spread inside an m as well: 128-row blocks of very different size
+    ll = np.concatenate([np.arange(m, lmax + 1) for m in range(lmax + 1)])
+    wild *= 10.0 ** (((ll // 64) % 3) * 6.0 - 6.0)
+    alms = np.stack([base[0] * 1e-25, base[1] * 1e25, base[2], wild])
+    plan = P.Plan(lmax, g, nmaps=4, precision=prec)
+    mp = plan.alm2map(torch.from_numpy(alms).to(_dev())).cpu().numpy()
+    for i in range(4):
+        em = ref.alm2map(lmax, g, alms[i])
+        assert np.all(np.isfinite(mp[i])), i
+        assert _rel(mp[i], em) < TOL, i

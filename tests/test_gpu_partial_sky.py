@@ -23,7 +23,7 @@ from oracle import ref
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-TOL = {"fp64": 1e-12, "fp32_mfma": 1e-6, "bf16x3_mfma": 1e-6}
+TOL = {"fp64": 1e-12, "fp32_mfma": 1e-6, "bf16x3_mfma": 1e-6, "f16x2_mfma": 1e-6}
 PRECS = list(TOL)
 SENTINEL = 7.25
 
