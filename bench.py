@@ -11,7 +11,11 @@ Workloads (seeded Gaussian a_lm, C_l = 1/(l(l+1)), HEALPix rings,
 One step is the whole transform of one batch through the C ABI (coefficient
 prescale, Legendre stage, per-ring Fourier synthesis).  Stage durations come
 from HIP events the library records on the launch stream around each kernel.
-Prints one JSON line.
+Beside the headline: the l_max 64 / nside 32 single map (launch-latency
+bound), the 64-map uneven batch (one persistent launch replayed from a HIP
+graph), map2alm, the differentiation workload, each mixed map's error
+against the CPU oracle on sampled rings, and the oracle's own rate on the
+host (all threads and one thread).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -198,6 +202,36 @@ def run_transfer(plan, alms_np, torch, np, reps=3):
             "buffers": "pinned host (hipHostMalloc through torch), one stream, no overlap"}
 
 
+def run_small(torch, np, W, dev, reps=200):
+    """l_max 64, HEALPix nside 32, one FP64 map: launch-latency bound, timed
+    over `reps` back-to-back transforms; checked against the oracle."""
+    from oracle import ref
+    from paper_1010_1260_amd import Plan
+    c = W.CONFIGS[1]
+    L, N = c["lmax"], c["nside"]
+    geom = W.healpix_geometry(N)
+    plan = Plan(L, geom, device=dev)
+    a_np = W.config_alm(1)
+    a = torch.from_numpy(a_np).to(dev).reshape(1, -1)
+    out = torch.empty((1, plan.npix), dtype=torch.float64, device=dev)
+    for _ in range(10):
+        plan.alm2map(a, out=out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.alm2map(a, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    exp = ref.alm2map(L, geom, a_np)
+    got = out[0].cpu().numpy()
+    return {"lmax": L, "nside": N, "maps": 1, "precision": "fp64", "reps": reps,
+            "ms_per_map": ms, "maps_per_s": 1e3 / ms,
+            "rel_err_vs_oracle": float(np.linalg.norm(got - exp) / np.linalg.norm(exp))}
+
+
 def run_grad(args, torch, np, W, dev):
     """The differentiation workload: 8 maps, l_max 1024, nside 512, loss
     0.5 ||alm2map(a) - d||^2 with d ~ N(0, 1) per pixel; one step = forward
@@ -245,9 +279,11 @@ def main() -> int:
     ap.add_argument("--no-transfer", action="store_true",
                     help="skip the transfer-inclusive (pinned host buffers) timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--uneven", action="store_true",
-                    help="also time the batched uneven workload (64 maps, l_max in "
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the batched uneven workload (64 maps, l_max in "
                          "{256..2048}, one persistent launch, autotuned, graph replay)")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the l_max 64 / nside 32 single-map timing")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, copy this many MiB device to device (a copy of known "
                          "size for scaling hardware byte counters)")
@@ -328,7 +364,10 @@ def main() -> int:
 
     npairs = (mixed or fp64)["plan"].npairs
     nalm = (mixed or fp64)["plan"].nalm
-    fft_bytes_per_map = 16.0 * geom.nrings * (Lmax + 1) + 8.0 * geom.npix
+    # Fourier stage, algorithmic bytes per map: Delta read once (complex128 in
+    # FP64, complex64 in the mixed forms) and the map written once
+    fft_bytes_fp64 = 16.0 * geom.nrings * (Lmax + 1) + 8.0 * geom.npix
+    fft_bytes_mixed = 8.0 * geom.nrings * (Lmax + 1) + 8.0 * geom.npix
     if fp64 is not None:
         t = fp64["wall"] / args.steps
         leg = float(fp64["st"][1])
@@ -342,7 +381,8 @@ def main() -> int:
                                   "frac": flops / (leg * 1e-3) / PEAK_FP64,
                                   "kernel": f"k_legendre_fwd<{fp64['plan'].config}>",
                                   "flops_per_launch": flops},
-            "fourier_GBps": fft_bytes_per_map / (float(fp64["st"][2]) * 1e-3) / 1e9,
+            "fourier_GBps": fft_bytes_fp64 / (float(fp64["st"][2]) * 1e-3) / 1e9,
+            "fourier_frac_hbm": fft_bytes_fp64 / (float(fp64["st"][2]) * 1e-3) / PEAK_HBM,
             "map2alm": fp64["map2alm"],
         }
         res["fp64"] = fp64_info
@@ -382,10 +422,14 @@ def main() -> int:
             "stages_ms": fb["stages_ms"],
             "roofline": fb["roofline"],
             "mixed_forms": forms,
-            "fourier_stage": {"bytes_per_launch": fft_bytes_per_map * B,
-                              "achieved_GBps": fft_bytes_per_map * B /
+            "fourier_stage": {"bytes_per_launch": fft_bytes_mixed * B,
+                              "bytes_note": "complex64 Delta read once + float64 map written "
+                                            "once; the stage also transposes Delta to "
+                                            "ring-contiguous order (its traffic is not "
+                                            "counted as algorithmic)",
+                              "achieved_GBps": fft_bytes_mixed * B /
                               (fb["stages_ms"]["ring_synthesis"] * 1e-3) / 1e9,
-                              "frac_hbm": fft_bytes_per_map * B /
+                              "frac_hbm": fft_bytes_mixed * B /
                               (fb["stages_ms"]["ring_synthesis"] * 1e-3) / PEAK_HBM},
         })
         if fp64 is not None:
@@ -411,8 +455,10 @@ def main() -> int:
                                "lmax": Lmax, "nside": N, "nmaps": 1, "precision": "fp64"},
                     "roofline": dict(res["fp64"]["legendre_roofline"], traffic=None)})
 
-    if args.uneven:
+    if not args.no_uneven:
         res["uneven_batch"] = run_uneven(args, torch, np, W, dev)
+    if not args.no_small:
+        res["small_lmax64_nside32"] = run_small(torch, np, W, dev)
     if args.only in ("all", "fp64"):
         res["differentiation"] = run_grad(args, torch, np, W, dev)
 
@@ -421,15 +467,30 @@ def main() -> int:
         rings = np.arange(0, geom.nrings, args.cpu_ring_stride)
         th = ref.max_threads()
         tc0 = time.perf_counter()
-        exp = ref.alm2map_rings(Lmax, geom, alms_np[0], rings)
+        exp = ref.alm2map_rings(Lmax, geom, alms_np[0], rings, nthreads=th)
         tc = time.perf_counter() - tc0
         # every ring costs the same Legendre work: scale the sample to a map
         cpu_maps_per_s = (len(rings) / geom.nrings) / tc
+        # one thread on a smaller sample (every 128th ring)
+        rings1 = np.arange(0, geom.nrings, 128)
+        t10 = time.perf_counter()
+        ref.alm2map_rings(Lmax, geom, alms_np[0], rings1, nthreads=1)
+        t1 = time.perf_counter() - t10
+        try:
+            aff = len(os.sched_getaffinity(0))
+        except (AttributeError, OSError):
+            aff = None
         res["cpu_baseline"] = {"value": cpu_maps_per_s, "unit": "maps/s", "cores": th,
                                "kind": "oracle",
                                "sample": f"map 0, {len(rings)} of {geom.nrings} rings (every "
                                          f"{args.cpu_ring_stride}th), {tc:.1f} s wall, scaled "
-                                         f"by ring count; CPU: {_cpu_model()}"}
+                                         f"by ring count; CPU: {_cpu_model()}",
+                               "threads_used": th, "os_cpu_count": os.cpu_count(),
+                               "affinity_cpus": aff,
+                               "value_1thread": (len(rings1) / geom.nrings) / t1,
+                               "sample_1thread": f"map 0, {len(rings1)} rings (every 128th), "
+                                                 f"{t1:.1f} s wall",
+                               "compiler": " ".join(ref.COMPILE_FLAGS)}
         errs = {}
         for name, runinfo in list(mixed_runs.items()) + [("fp64", fp64)]:
             if runinfo is None:
@@ -442,6 +503,26 @@ def main() -> int:
                 den += float(np.sum(e ** 2))
             errs[name] = float(np.sqrt(num / den))
         res["rel_err_vs_oracle_sampled_rings_map0"] = errs
+        # every map of the mixed batch against the oracle on every 64th ring
+        if mixed_runs:
+            rings64 = np.arange(0, geom.nrings, 64)
+            exps = [ref.alm2map_rings(Lmax, geom, alms_np[i], rings64, nthreads=th)
+                    for i in range(B)]
+            per = {}
+            for name, runinfo in mixed_runs.items():
+                outc = runinfo["out"].cpu().numpy()
+                e_i = []
+                for i in range(B):
+                    num = den = 0.0
+                    for r, e in zip(rings64, exps[i]):
+                        s0, n = int(geom.ringstart[r]), int(geom.nphi[r])
+                        num += float(np.sum((outc[i, s0:s0 + n] - e) ** 2))
+                        den += float(np.sum(e ** 2))
+                    e_i.append(float(np.sqrt(num / den)))
+                per[name] = {"max": max(e_i), "mean": float(np.mean(e_i)), "per_map": e_i}
+            res["rel_err_vs_oracle_per_map"] = {
+                "rings": f"{len(rings64)} of {geom.nrings} (every 64th), all {B} maps",
+                "forms": per}
     print(json.dumps(res), flush=True)
     return 0
 

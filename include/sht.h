@@ -229,7 +229,12 @@ sht_status sht_alm2map_adjoint(sht_plan_t plan, const double *map, double *alm,
 /* The two stages on their own (same kernels as sht_alm2map).
  * delta: device complex128 [nmaps][nm][nrings], Delta_m(theta_r) of
  * Eq. (DeltaDef) for the i-th m of the set at [b][i][r] (rings contiguous:
- * the Legendre stage writes whole runs of rings per m). */
+ * the Legendre stage writes whole runs of rings per m).
+ * The mixed forms keep Delta as complex64 inside sht_alm2map (the precision
+ * of their FP32 sums); sht_alm2delta of a mixed plan writes that complex64
+ * Delta into the workspace and widens it exactly into `delta`, so it needs
+ * sht_plan_info.forward_workspace_bytes (FP64 plans: the coefficient part
+ * only).  sht_delta2map always reads complex128. */
 sht_status sht_alm2delta(sht_plan_t plan, const double *alm, double *delta,
                          void *ws, size_t ws_bytes, void *stream);
 sht_status sht_delta2map(sht_plan_t plan, const double *delta, double *map, void *stream);

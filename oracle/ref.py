@@ -34,14 +34,16 @@ _lock = threading.Lock()
 _lib = None
 
 
+COMPILE_FLAGS = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                 "-fno-fast-math", "-std=c11", "-D_GNU_SOURCE"]
+
+
 def build(force: bool = True) -> str:
     """Compile the C oracle with gcc (FP64, no contraction, OpenMP)."""
     os.makedirs(os.path.dirname(_SO), exist_ok=True)
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call([
-            "gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-            "-fno-fast-math", "-std=c11", "-D_GNU_SOURCE", _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call([*COMPILE_FLAGS, _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 

@@ -43,7 +43,7 @@ struct sht_batch_s {
     BatchMap *d_maps;
     BatchTile *d_tiles[3];           // work lists for 1, 2, 4 chains per lane
     int ntiles[3];
-    BatchClass cls[sht::kNumRingClasses];
+    BatchClass cls[sht::kNumSynthClasses];
     long long max_nalm;
     size_t ws_bytes;
     int chains;                      // launch shape in use
@@ -72,7 +72,7 @@ void free_batch(sht_batch_s *b)
     if (b->d_maps) (void)hipFree(b->d_maps);
     for (int i = 0; i < 3; ++i)
         if (b->d_tiles[i]) (void)hipFree(b->d_tiles[i]);
-    for (int c = 0; c < sht::kNumRingClasses; ++c)
+    for (int c = 0; c < sht::kNumSynthClasses; ++c)
         if (b->cls[c].d_items) (void)hipFree(b->cls[c].d_items);
     if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -172,15 +172,18 @@ sht_status sht_plan_batch(sht_batch_t *out, const sht_plan_t *plans, int32_t n)
     // Fourier work items per ring size class, map by map and ring by ring:
     // the workgroups that run together then read neighbouring rings of one
     // map, whose Delta entries share cache lines
-    for (int c = 0; c < sht::kNumRingClasses && st == SHT_OK; ++c) {
+    for (int c = 0; c < sht::kNumSynthClasses && st == SHT_OK; ++c) {
         std::vector<int2> items;
         sht::RingLds lds = {};
         for (int i = 0; i < n; ++i) {
             const sht_plan_s *p = plans[i];
             for (int r = 0; r < p->nrings; ++r)
-                if (p->ring_class[r] == c) {
+                if (p->ring_sclass[r] == c) {
                     items.push_back(make_int2(i, r));
-                    sht::ring_lds_add(lds, c, p->ring_n[r], p->ring_nb[r], p->ring_need[r]);
+                    if (c == sht::kFastClass)
+                        sht::fast_lds_add(lds, p->ring_n[r], p->mmax);
+                    else
+                        sht::ring_lds_add(lds, c, p->ring_n[r], p->ring_nb[r], p->ring_need[r]);
                 }
         }
         b->cls[c].count = (int)items.size();

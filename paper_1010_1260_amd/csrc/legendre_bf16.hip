@@ -404,7 +404,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_legendre_mfma_bf16x3(
     const int *__restrict__ mval, const long long *__restrict__ moff,
     const long long *__restrict__ boff, const double *__restrict__ mu, int nm, int nmpairs,
     int lmax, const double *__restrict__ A, const v4u *__restrict__ Bb, long long nblocks,
-    double *__restrict__ delta, int nrings, int nmaps, long long total)
+    float2 *__restrict__ delta, int nrings, int nmaps, long long total)
 {
     __shared__ __attribute__((aligned(16))) char ldsA[kBufBytes];
     __shared__ __attribute__((aligned(16))) char ldsB[kBufBytes];
@@ -471,7 +471,7 @@ hipError_t launch_prescale_bf16x3(const sht_plan_s *p, const double *alm, void *
     return hipGetLastError();
 }
 
-hipError_t launch_legendre_mfma_bf16x3(const sht_plan_s *p, const void *Bb, double2 *delta,
+hipError_t launch_legendre_mfma_bf16x3(const sht_plan_s *p, const void *Bb, float2 *delta,
                                        hipStream_t st)
 {
     const int pblocks = (p->npairs + 63) / 64;
@@ -483,7 +483,7 @@ hipError_t launch_legendre_mfma_bf16x3(const sht_plan_s *p, const void *Bb, doub
     hipLaunchKernelGGL(k_legendre_mfma_bf16x3, dim3((unsigned)total), dim3(kThreads), 0, st,
                        p->d_pairs, p->npairs, pgroups, p->d_mval, p->d_moff, p->d_boff, p->d_mu, p->nm,
                        nmpairs, p->lmax, p->d_A, reinterpret_cast<const v4u *>(Bb),
-                       bf16_blocks(p), reinterpret_cast<double *>(delta), p->nrings, p->nmaps,
+                       bf16_blocks(p), delta, p->nrings, p->nmaps,
                        total);
     return hipGetLastError();
 }

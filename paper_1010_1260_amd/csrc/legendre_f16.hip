@@ -474,7 +474,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_legendre_mfma_f16x2(
     const int *__restrict__ mval, const long long *__restrict__ moff,
     const long long *__restrict__ soff, const double *__restrict__ mu, int nm, int nmpairs,
     int lmax, const double *__restrict__ A, const double *__restrict__ Asb,
-    const v4u *__restrict__ Bb, long long nsuper, double *__restrict__ delta, int nrings,
+    const v4u *__restrict__ Bb, long long nsuper, float2 *__restrict__ delta, int nrings,
     int nmaps, long long total)
 {
     __shared__ __attribute__((aligned(16))) char ldsA[kBufBytes];
@@ -534,7 +534,7 @@ hipError_t launch_prescale_f16x2(const sht_plan_s *p, const double *alm, void *B
     return hipGetLastError();
 }
 
-hipError_t launch_legendre_mfma_f16x2(const sht_plan_s *p, const void *Bb, double2 *delta,
+hipError_t launch_legendre_mfma_f16x2(const sht_plan_s *p, const void *Bb, float2 *delta,
                                       hipStream_t st)
 {
     const int pblocks = (p->npairs + 63) / 64;
@@ -547,7 +547,7 @@ hipError_t launch_legendre_mfma_f16x2(const sht_plan_s *p, const void *Bb, doubl
                        p->d_pairs, p->npairs, pgroups, p->d_mval, p->d_moff, p->d_soff, p->d_mu,
                        p->nm, nmpairs, p->lmax, p->d_A, p->d_Asb,
                        reinterpret_cast<const v4u *>(Bb), p->nsuper,
-                       reinterpret_cast<double *>(delta), p->nrings, p->nmaps, total);
+                       delta, p->nrings, p->nmaps, total);
     return hipGetLastError();
 }
 

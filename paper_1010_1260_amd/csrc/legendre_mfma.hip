@@ -363,7 +363,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_legendre_mfma_f32(
     const int *__restrict__ mval, const long long *__restrict__ moff,
     const long long *__restrict__ boff16, const double *__restrict__ mu, int nm, int nmpairs,
     int lmax, const double *__restrict__ A, const float *__restrict__ Bp, long long nblocks,
-    double *__restrict__ delta, int nrings, int nmaps, long long total)
+    float2 *__restrict__ delta, int nrings, int nmaps, long long total)
 {
     __shared__ __attribute__((aligned(16))) char ldsA[kBufBytes];
     __shared__ __attribute__((aligned(16))) char ldsB[kBufBytes];
@@ -424,7 +424,7 @@ hipError_t launch_prescale_f32(const sht_plan_s *p, const double *alm, float *Bp
     return hipGetLastError();
 }
 
-hipError_t launch_legendre_mfma_f32(const sht_plan_s *p, const float *Bp, double2 *delta,
+hipError_t launch_legendre_mfma_f32(const sht_plan_s *p, const float *Bp, float2 *delta,
                                     hipStream_t st)
 {
     const int pblocks = (p->npairs + 63) / 64;
@@ -436,7 +436,7 @@ hipError_t launch_legendre_mfma_f32(const sht_plan_s *p, const float *Bp, double
     hipLaunchKernelGGL(k_legendre_mfma_f32, dim3((unsigned)total), dim3(kThreads), 0, st,
                        p->d_pairs, p->npairs, pgroups, p->d_mval, p->d_moff, p->d_boff16,
                        p->d_mu, p->nm, nmpairs, p->lmax, p->d_A, Bp, p->nblk16,
-                       reinterpret_cast<double *>(delta), p->nrings, p->nmaps, total);
+                       delta, p->nrings, p->nmaps, total);
     return hipGetLastError();
 }
 

@@ -95,14 +95,16 @@ __device__ __forceinline__ void block16_dead_g(double x, double &ua, double &ub,
 // Delta of one m.  D layout of a 32x32 tile: column = lane % 32 (the ring
 // pair), row = 8 (r/4) + 4 (lane/32) + r % 4 = 2 map + Re/Im, so a lane owns
 // 8 complex values of one pair and a half-wave stores 32 consecutive rings
-// of Delta [map][m][ring].
-__device__ __forceinline__ void m_store(const MfmaTiles &tot, int i, double *__restrict__ delta,
+// of Delta [map][m][ring].  The parity sums are FP32; north (E + O) and
+// south (E - O) are formed exactly in FP64 and rounded once to FP32, the
+// precision the contraction carries, so Delta is stored as complex64.
+__device__ __forceinline__ void m_store(const MfmaTiles &tot, int i, float2 *__restrict__ delta,
                                         const PairDesc *__restrict__ pairs, int npairs, int pb,
                                         int grp, int nmaps, int nrings, int nm, int lane)
 {
     const int hi = lane >> 5;
     const int col = lane & 31;
-    double2 *__restrict__ d2 = reinterpret_cast<double2 *>(delta);
+    float2 *__restrict__ d2 = delta;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const v16f &E = h ? tot.e1 : tot.e0;
@@ -115,10 +117,11 @@ __device__ __forceinline__ void m_store(const MfmaTiles &tot, int i, double *__r
                 const int map = grp * 16 + 4 * (r >> 2) + 2 * hi + ((r & 3) >> 1);
                 if (map < nmaps) {
                     const double er = E[r], ei = E[r + 1], orr = O[r], oi = O[r + 1];
-                    d2[((long long)map * nm + i) * nrings + d.rn] = make_double2(er + orr, ei + oi);
+                    d2[((long long)map * nm + i) * nrings + d.rn] =
+                        make_float2((float)(er + orr), (float)(ei + oi));
                     if (d.rs >= 0)
                         d2[((long long)map * nm + i) * nrings + d.rs] =
-                            make_double2(er - orr, ei - oi);
+                            make_float2((float)(er - orr), (float)(ei - oi));
                 }
             }
         }

@@ -14,10 +14,17 @@
 // Analysis (adjoint): G_k = sum_j g_j e^{-2 pi i j k / n} by the reverse
 // construction, then Dt_m = c_m e^{-i m phi0} G_{m mod n} (c_0 = 1, c_m = 2).
 //
-// One workgroup per ring and map; the whole ring lives in LDS.  Rings are
-// grouped by FFT length into three size classes (up to 2048, 4096 and 8192
-// points) run by 256-, 512- and 1024-thread workgroups, each with an LDS
-// layout computed on the host for the class.  DFTs of 7-smooth length run as
+// One workgroup per ring and map; the whole ring lives in LDS.  The
+// synthesis of even rings whose half length is 7-smooth and at most 4096
+// (every HEALPix belt ring, and the caps' smooth rings) takes a fast path: a
+// persistent 256-thread kernel that loads a ring's modes all at once (the
+// next ring's while the current one is transformed), folds them through a
+// padded LDS buffer and runs Stockham passes of radix 16, 8, 4, 2, 7, 5, 3
+// with the butterflies held in registers, the half-length pre-processing
+// fused into the first pass and the pixels stored from the last.  The other
+// rings are grouped by FFT length into three size classes (up to 2048, 4096
+// and 8192 points) run by 256-, 512- and 1024-thread workgroups, each with an
+// LDS layout computed on the host for the class.  There, DFTs of 7-smooth length run as
 // a Stockham auto-sort FFT (radices 8, 4, 2, 3, 5 and 7; every pass loads its
 // butterfly inputs into registers, barriers, and stores in place, so one LDS
 // buffer suffices).  Other lengths use Bluestein's chirp-z algorithm with a
@@ -89,6 +96,37 @@ __device__ inline void small_dft(double2 (&v)[R], int sign)
         v[2] = csub(s02, s13);
         v[1] = cadd(d02, d13);
         v[3] = csub(d02, d13);
+    } else if constexpr (R == 16) {
+        // 16 = 4 x 4: r = 4a + b, k = c + 4d, w^(rk) = w4^(ac) w16^(bc) w4^(bd)
+        double2 u[4][4];   // u[b][c]
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            double2 t[4] = {v[b], v[4 + b], v[8 + b], v[12 + b]};
+            small_dft<4>(t, sign);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) u[b][c] = t[c];
+        }
+        constexpr double c1 = 0x1.d906bcf328d46p-1;  // cos(pi/8), correctly rounded
+        constexpr double s1 = 0x1.87de2a6aea963p-2;  // sin(pi/8)
+        constexpr double hh = 0x1.6a09e667f3bcdp-1;  // 1/sqrt(2)
+        // w16^e = (cos, sign sin) of 2 pi e / 16 for e = b c, b, c in 1..3
+        const double sg = (double)sign;
+        u[1][1] = cmul(u[1][1], make_double2(c1, sg * s1));
+        u[1][2] = cmul(u[1][2], make_double2(hh, sg * hh));
+        u[1][3] = cmul(u[1][3], make_double2(s1, sg * c1));
+        u[2][1] = cmul(u[2][1], make_double2(hh, sg * hh));
+        u[2][2] = muli(u[2][2], sign);
+        u[2][3] = cmul(u[2][3], make_double2(-hh, sg * hh));
+        u[3][1] = cmul(u[3][1], make_double2(s1, sg * c1));
+        u[3][2] = cmul(u[3][2], make_double2(-hh, sg * hh));
+        u[3][3] = cmul(u[3][3], make_double2(-c1, -sg * s1));
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double2 t[4] = {u[0][c], u[1][c], u[2][c], u[3][c]};
+            small_dft<4>(t, sign);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) v[c + 4 * d] = t[d];
+        }
     } else if constexpr (R == 8) {
         // two radix-4 DFTs of the even and odd inputs, combined with w8^k
         double2 e[4] = {v[0], v[2], v[4], v[6]};
@@ -415,27 +453,51 @@ __device__ inline int xcd_logical(int b, int total)
     return x * q + (x < r ? x : r) + i;
 }
 
+// Work item -> (index in the class's ring list, map): map by map, ring by
+// ring, so that the workgroups running together read neighbouring rings of
+// one map (whose Delta entries share cache lines and DRAM pages).  Measured
+// faster than grouping a few rings' items of all maps together, which would
+// keep each ring's tables in L2 but spreads the Delta reads over all maps.
+__device__ inline void ring_item(long long it, int count, int &i, int &b)
+{
+    b = (int)(it / count);
+    i = (int)(it - (long long)b * count);
+}
+
 // Delta_m for mode m of a ring (zero for m outside the set); Delta is laid
-// out [m][ring], so the ring's modes are `dstride` entries apart.
-__device__ inline double2 load_mode(const double2 *__restrict__ drow, long long dstride,
+// out [m][ring], so the ring's modes are `dstride` entries apart.  DT is the
+// stored element: complex128, or complex64 from the mixed-precision
+// Legendre stage (widened exactly).
+__device__ inline double2 widen(double2 v) { return v; }
+__device__ inline double2 widen(float2 v) { return make_double2((double)v.x, (double)v.y); }
+
+template <typename DT>
+__device__ inline double2 load_mode(const DT *__restrict__ drow, long long dstride,
                                     const int *__restrict__ minv, int mcontig, int m)
 {
     const int i = mcontig ? m : minv[m];
-    return (i >= 0) ? drow[(long long)i * dstride] : make_double2(0.0, 0.0);
+    return (i >= 0) ? widen(drow[(long long)i * dstride]) : make_double2(0.0, 0.0);
 }
 
 // Synthesis: one workgroup per (ring of this size class, map).  LDS: the
 // spectrum / FFT buffer, the twiddle tables and the alias staging slots
 // (RingLds).
 // Synthesis of one ring: drow = its Delta_m row, out = its first pixel.
-template <int NT, int MAXN, bool REG, bool PRIV>
-__device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, const RingTables &rt, const RingDesc &d,
-                           const double2 *__restrict__ pool, const double2 *__restrict__ drow,
-                           long long dstride, const int *__restrict__ minv, int mcontig, int mmax,
-                           double *__restrict__ out)
+// Padded LDS indexing of the fast path's spectrum / FFT buffer.
+struct PadIdx {   // one spare entry per 16 (bank-conflict-free strided stores)
+    __device__ static int at(int i) { return i + (i >> 4); }
+};
+
+// Fold a ring's modes into its spectrum F_k, k = 0..kmax (Eq. Delta2map with
+// the wrap rule of Sec. 2.2.2; ends with a barrier).  drow = the ring's
+// Delta_m row, the i-th m of the set at drow[i dstride].
+template <int NT, typename DT>
+__device__ __attribute__((always_inline)) inline void fold_ring(double2 *buf, const RingDesc &d,
+                                                                const DT *__restrict__ drow,
+                                                                long long dstride,
+                                                                const int *__restrict__ minv,
+                                                                int mcontig, int mmax)
 {
-    Chirps<NT, MAXN, REG> ch;
-    ring_tables_load<NT, MAXN, REG>(rt, d, pool, ch);
     const int n = d.n;
     const bool even = (n % 2) == 0;
     const int h = n / 2;
@@ -577,6 +639,21 @@ __device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, c
         }
     }
     __syncthreads();
+}
+
+template <int NT, int MAXN, bool REG, bool PRIV, typename DT>
+__device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, const RingTables &rt, const RingDesc &d,
+                           const double2 *__restrict__ pool, const DT *__restrict__ drow,
+                           long long dstride, const int *__restrict__ minv, int mcontig, int mmax,
+                           double *__restrict__ out)
+{
+    Chirps<NT, MAXN, REG> ch;
+    ring_tables_load<NT, MAXN, REG>(rt, d, pool, ch);
+    const int n = d.n;
+    const bool even = (n % 2) == 0;
+    const int h = n / 2;
+    const int tid = threadIdx.x;
+    fold_ring<NT>(buf, d, drow, dstride, minv, mcontig, mmax);
     if (even) {
         for (int k = tid; k <= h / 2; k += NT) {
             const int k2 = h - k;
@@ -606,22 +683,345 @@ __device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, c
     }
 }
 
-template <int NT, int MAXN>
-__global__ __launch_bounds__(NT, 4) void k_ring_synth(
-    const int *__restrict__ ids, const RingDesc *__restrict__ rings,
-    const double2 *__restrict__ pool, const double2 *__restrict__ delta,
+
+// ---------------------------------------------------------------------------
+// Fast path of the synthesis: even rings whose half length h is 7-smooth and
+// at most kFastMaxH.  The spectrum sits in a padded LDS buffer (PadIdx), each
+// Stockham pass holds its butterflies in registers (radix 16, 8, 4, 2, 7, 5,
+// 3 from the ring's pass list), the half-length pre-processing Z_k is formed
+// while the first pass loads its inputs, and the last pass writes the pixels
+// straight from registers: per ring one fold, one barrier pair per inner
+// pass and no other LDS round trip.
+//
+// One pass of radix R over the h-point buffer (input index j + r h/R,
+// output index (j / Ns) Ns R + j % Ns + r Ns).  T: the ring's n-th roots.
+template <int R, int NT>
+__device__ __attribute__((always_inline)) inline void fast_pass(double2 *buf, const double2 *T,
+                                                                int h, int Ns, bool first,
+                                                                bool last, double *__restrict__ out)
+{
+    constexpr int MAXQ = fast_maxq(R);   // the plan admits h / R <= MAXQ * kFastThreads
+    const int nb = h / R;
+    const int tstep0 = (h / (Ns * R)) * 2;   // T holds the roots of n = 2 h
+    const unsigned magic = (unsigned)((0x100000000ull + (unsigned)Ns - 1) / (unsigned)Ns);
+    // an opaque copy of the thread index: the passes run in a loop over the
+    // ring's radix list, and address arithmetic hoisted out of every radix's
+    // case would stay live across all of them
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    double2 v[MAXQ][R];
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) {
+        const int j = tid + q * NT;
+        if (j < nb) {
+            if (first) {
+                // Z_k = (F_k + conj F_{h-k}) + i e^{2 pi i k/n} (F_k - conj F_{h-k})
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int k = j + r * nb;
+                    const double2 Fk = buf[PadIdx::at(k)], Fk2 = buf[PadIdx::at(h - k)];
+                    const double2 e1 = cadd(Fk, conjd(Fk2)), o1 = csub(Fk, conjd(Fk2));
+                    v[q][r] = cadd(e1, muli(cmul(tw_at(T, k), o1), +1));
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[q][r] = buf[PadIdx::at(j + r * nb)];
+            }
+            if (Ns > 1) {
+                const int jq = (int)__umulhi((unsigned)j, magic);
+                const int ts = tstep0 * (j - jq * Ns);
+                if (ts != 0) {
+                    const double2 w1 = tw_at(T, ts);
+                    double2 wr = w1;
+#pragma unroll
+                    for (int r = 1; r < R; ++r) {
+                        v[q][r] = cmul(v[q][r], wr);
+                        wr = cmul(wr, w1);
+                    }
+                }
+            }
+            small_dft<R>(v[q], +1);
+        }
+    }
+    if (last) {
+        // Ns R = h: j < Ns, output z_{j + r nb} = pixels 2 (j + r nb), 2 (j + r nb) + 1
+        const bool al = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+        double2 *o2 = reinterpret_cast<double2 *>(out);
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+            const int j = tid + q * NT;
+            if (j < nb) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int i = j + r * nb;
+                    if (al) {
+                        o2[i] = v[q][r];
+                    } else {
+                        out[2 * i] = v[q][r].x;
+                        out[2 * i + 1] = v[q][r].y;
+                    }
+                }
+            }
+        }
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+            const int j = tid + q * NT;
+            if (j < nb) {
+                const int jq = (Ns == 1) ? j : (int)__umulhi((unsigned)j, magic);
+                const int base = jq * Ns * R + (j - jq * Ns);
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[PadIdx::at(base + r * Ns)] = v[q][r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Fold of a fast-path ring (modes m = 0..mmax <= kFastMaxModes - 1, n even).
+// Every thread loads its modes m = tid + q NT at once, multiplies them by
+// e^{i m phi0} and stores them at buf[PadIdx(m)]; then bin k sums its
+// aliases m = k + j n and conj of m = j n - k in a fixed order (j ascending,
+// direct before mirrored), in place: below index n/2 + 1 the buffer entry m
+// is read only by bin m, whose own thread then overwrites it with F_m.  Rings
+// with fewer bins than threads split each bin's aliases over G = NT / bins
+// threads and add the G partial sums in a fixed order.  Ends with a barrier.
+template <int NT>
+struct FastModes {
+    double2 v[kFastMaxModes / NT];
+};
+
+// Loads of the fold: modes m = tid + q NT of one ring (issued together).
+template <int NT, typename DT>
+__device__ __attribute__((always_inline)) inline void load_fast(FastModes<NT> &raw,
+                                                                const DT *__restrict__ drow,
+                                                                long long dstride,
+                                                                const int *__restrict__ minv,
+                                                                int mcontig, int mmax)
+{
+    constexpr int QM = kFastMaxModes / NT;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const int m = tid + q * NT;
+        raw.v[q] = (m <= mmax) ? load_mode(drow, dstride, minv, mcontig, m)
+                               : make_double2(0.0, 0.0);
+    }
+}
+
+template <int NT>
+__device__ __attribute__((always_inline)) inline void fold_fast(double2 *buf, const RingDesc &d,
+                                                                const FastModes<NT> &raw,
+                                                                int mmax)
+{
+    constexpr int QM = kFastMaxModes / NT;
+    const int tid = threadIdx.x;
+    double2 ph, step;   // e^{i tid phi0}, e^{i NT phi0}
+    {
+        double sn, cs;
+        sincos((double)tid * d.phi0, &sn, &cs);
+        ph = make_double2(cs, sn);
+        sincos((double)NT * d.phi0, &sn, &cs);
+        step = make_double2(cs, sn);
+    }
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const int m = tid + q * NT;
+        if (m <= mmax) {
+            double2 v = raw.v[q];
+            if (m == 0) v.y = 0.0;
+            buf[PadIdx::at(m)] = cmul(ph, v);
+        }
+        ph = cmul(ph, step);
+    }
+    __syncthreads();
+    const int n = d.n;
+    const int h = n / 2;
+    const int B = h + 1;
+    if (n > mmax) {
+        // at most one direct mode (m = k) and one mirrored mode (m = n - k)
+        for (int k = tid; k <= h; k += NT) {
+            double2 F = (k <= mmax) ? buf[PadIdx::at(k)] : make_double2(0.0, 0.0);
+            if (k >= 1 && n - k <= mmax) F = cadd(F, conjd(buf[PadIdx::at(n - k)]));
+            buf[PadIdx::at(k)] = F;
+        }
+    } else if (B >= NT) {
+        for (int k = tid; k <= h; k += NT) {
+            const int jmax = (mmax + k) / n;
+            double sr = 0.0, si = 0.0;
+            for (int j = 0; j <= jmax; ++j) {
+                if (k + j * n <= mmax) {
+                    const double2 v = buf[PadIdx::at(k + j * n)];
+                    sr += v.x; si += v.y;
+                }
+                if (j >= 1) {
+                    const double2 v = buf[PadIdx::at(j * n - k)];
+                    sr += v.x; si -= v.y;
+                }
+            }
+            buf[PadIdx::at(k)] = make_double2(sr, si);
+        }
+    } else {
+        const int G = NT / B;
+        const int kk = tid % B, g = tid / B;
+        double sr = 0.0, si = 0.0;
+        if (g < G) {
+            const int jmax = (mmax + kk) / n;
+            for (int j = g; j <= jmax; j += G) {
+                if (kk + j * n <= mmax) {
+                    const double2 v = buf[PadIdx::at(kk + j * n)];
+                    sr += v.x; si += v.y;
+                }
+                if (j >= 1) {
+                    const double2 v = buf[PadIdx::at(j * n - kk)];
+                    sr += v.x; si -= v.y;
+                }
+            }
+        }
+        __syncthreads();
+        if (g < G) buf[PadIdx::at(g * B + kk)] = make_double2(sr, si);
+        __syncthreads();
+        if (tid < B) {
+            // column tid of the partials; entry 0 of it is this thread's own
+            double tr = 0.0, ti = 0.0;
+            for (int q = 0; q < G; ++q) {
+                const double2 v = buf[PadIdx::at(q * B + tid)];
+                tr += v.x; ti += v.y;
+            }
+            buf[PadIdx::at(tid)] = make_double2(tr, ti);
+        }
+    }
+    __syncthreads();
+}
+
+template <int NT>
+__device__ __attribute__((always_inline)) inline void fft_fast(double2 *buf, const double2 *T,
+                                                               const RingDesc &d,
+                                                               double *__restrict__ out);
+
+// Synthesis of one fast-path ring: buf = padded spectrum buffer, T = LDS
+// twiddle table, out = the ring's first pixel.
+template <int NT, typename DT>
+__device__ __attribute__((always_inline)) inline void synth_fast(double2 *buf, double2 *T,
+                                                                 const RingDesc &d,
+                                                                 const double2 *__restrict__ pool,
+                                                                 const DT *__restrict__ drow,
+                                                                 long long dstride,
+                                                                 const int *__restrict__ minv,
+                                                                 int mcontig, int mmax,
+                                                                 double *__restrict__ out)
+{
+    load_tw<NT>(T, pool + d.tw, d.n);
+    FastModes<NT> raw;
+    load_fast<NT>(raw, drow, dstride, minv, mcontig, mmax);
+    fold_fast<NT>(buf, d, raw, mmax);
+    fft_fast<NT>(buf, T, d, out);
+}
+
+// The Stockham passes of a fast-path ring (after the fold) and the pixel
+// stores of the last one.
+template <int NT>
+__device__ __attribute__((always_inline)) inline void fft_fast(double2 *buf, const double2 *T,
+                                                               const RingDesc &d,
+                                                               double *__restrict__ out)
+{
+    const int h = d.n / 2;
+    int Ns = 1;
+    for (int p = 0; p < d.np; ++p) {
+        const int R = (int)((d.rads >> (5 * p)) & 31);
+        const bool first = p == 0, last = p == d.np - 1;
+        switch (R) {
+        case 16: fast_pass<16, NT>(buf, T, h, Ns, first, last, out); break;
+        case 8: fast_pass<8, NT>(buf, T, h, Ns, first, last, out); break;
+        case 4: fast_pass<4, NT>(buf, T, h, Ns, first, last, out); break;
+        case 2: fast_pass<2, NT>(buf, T, h, Ns, first, last, out); break;
+        case 7: fast_pass<7, NT>(buf, T, h, Ns, first, last, out); break;
+        case 5: fast_pass<5, NT>(buf, T, h, Ns, first, last, out); break;
+        default: fast_pass<3, NT>(buf, T, h, Ns, first, last, out); break;
+        }
+        Ns *= R;
+    }
+}
+
+//
+// Persistent: the grid is a multiple of 8 workgroups; the (map, ring) items,
+// in the order of ring_item, are split into 8 contiguous ranges, one per XCD
+// (workgroups are dealt to the XCDs round-robin), and the workgroups of an
+// XCD take its items in turn.  The loads of a workgroup's
+// next ring are issued before the Fourier passes of the current one, so that
+// their latency is hidden behind the passes.
+template <typename DT>
+__global__ __launch_bounds__(kFastThreads, 2) void k_ring_synth_fast(
+    const int *__restrict__ ids, int count, int nmaps, const RingDesc *__restrict__ rings,
+    const double2 *__restrict__ pool, const DT *__restrict__ delta,
     const int *__restrict__ minv, int mcontig, int mmax, int nm, int nrings,
     double *__restrict__ map, long long npix, RingLds lds)
 {
     extern __shared__ double2 buf[];
-    const int r = ids[xcd_logical(blockIdx.x, gridDim.x)];
-    const long long b = blockIdx.y;
+    double2 *T = buf + lds.fft_entries;
+    const long long total = (long long)count * nmaps;
+    const int per = (int)(gridDim.x / 8);
+    const int x = (int)(blockIdx.x % 8), w = (int)(blockIdx.x / 8);
+    const long long hi = total * (x + 1) / 8;
+    long long it = total * x / 8 + w;
+    if (it >= hi) return;
+    int i, bi;
+    ring_item(it, count, i, bi);
+    long long b = bi;
+    int r = ids[i];
+    FastModes<kFastThreads> raw;
+    load_fast<kFastThreads>(raw, delta + b * nm * nrings + r, nrings, minv, mcontig, mmax);
+    for (bool first = true;; first = false) {
+        const RingDesc d = rings[r];
+        double *out = map + b * npix + d.start;
+        if (!first) __syncthreads();   // the previous ring's last pass has read buf and T
+        load_tw<kFastThreads>(T, pool + d.tw, d.n);
+        fold_fast<kFastThreads>(buf, d, raw, mmax);
+        const long long nx = it + per;
+        if (nx < hi) {
+            ring_item(nx, count, i, bi);
+            b = bi;
+            r = ids[i];
+            load_fast<kFastThreads>(raw, delta + b * nm * nrings + r, nrings, minv, mcontig, mmax);
+        }
+        fft_fast<kFastThreads>(buf, T, d, out);
+        if (nx >= hi) break;
+        it = nx;
+    }
+}
+
+__global__ __launch_bounds__(kFastThreads, 2) void k_ring_synth_batch_fast(
+    const int2 *__restrict__ items, const BatchMap *__restrict__ maps,
+    double *const *__restrict__ outs, const char *__restrict__ ws, RingLds lds)
+{
+    extern __shared__ double2 buf[];
+    const int2 it = items[xcd_logical(blockIdx.x, gridDim.x)];
+    const BatchMap &bm = maps[it.x];
+    const RingDesc d = bm.rings[it.y];
+    const double2 *delta = reinterpret_cast<const double2 *>(ws + bm.delta_off);
+    synth_fast<kFastThreads>(buf, buf + lds.fft_entries, d, bm.pool, delta + it.y, bm.nrings,
+                             bm.minv, bm.mcontig, bm.mmax, outs[it.x] + d.start);
+}
+
+template <int NT, int MAXN, typename DT>
+__global__ __launch_bounds__(NT, 4) void k_ring_synth(
+    const int *__restrict__ ids, int count, int nmaps, const RingDesc *__restrict__ rings,
+    const double2 *__restrict__ pool, const DT *__restrict__ delta,
+    const int *__restrict__ minv, int mcontig, int mmax, int nm, int nrings,
+    double *__restrict__ map, long long npix, RingLds lds)
+{
+    extern __shared__ double2 buf[];
+    int i, bi;
+    ring_item(xcd_logical(blockIdx.x, gridDim.x), count, i, bi);
+    const int r = ids[i];
+    const long long b = bi;
     const RingDesc d = rings[r];
     double2 *tw = buf + lds.fft_entries;
     const RingTables rt = {tw, tw + lds.tw_entries};
     synth_ring<NT, MAXN, false, false>(buf, rt, d,
-                               pool, delta + b * nm * nrings + r, nrings, minv, mcontig, mmax,
-                               map + b * npix + d.start);
+                               pool, delta + b * nm * nrings + r, nrings, minv,
+                               mcontig, mmax, map + b * npix + d.start);
 }
 
 // Batched synthesis: work item (map, ring) of a batch of plans.
@@ -754,17 +1154,18 @@ hipError_t set_lds(const void *fn, size_t bytes)
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int NT, int MAXN>
-hipError_t synth_class(const sht_plan_s *p, int c, const double2 *delta, double *map,
-                       hipStream_t st)
+template <int NT, int MAXN, typename DT>
+hipError_t synth_class(const sht_plan_s *p, int c, const DT *delta, double *map, hipStream_t st)
 {
-    const RingClass &rc = p->cls[c];
+    const RingClass &rc = p->scls[c];
     if (rc.count == 0) return hipSuccess;
     const size_t lds = (size_t)rc.lds.total() * sizeof(double2);
-    hipError_t e = set_lds((const void *)k_ring_synth<NT, MAXN>, lds);
+    hipError_t e = set_lds((const void *)k_ring_synth<NT, MAXN, DT>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_ring_synth<NT, MAXN>), dim3((unsigned)rc.count, (unsigned)p->nmaps),
-                       dim3(NT), lds, st, rc.d_ids, p->d_rings, p->d_pool, delta, p->d_minv,
+    const long long items = (long long)rc.count * p->nmaps;
+    if (items > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_ring_synth<NT, MAXN, DT>), dim3((unsigned)items), dim3(NT), lds, st,
+                       rc.d_ids, rc.count, p->nmaps, p->d_rings, p->d_pool, delta, p->d_minv,
                        p->mcontig, p->mmax, p->nm, p->nrings, map, p->npix, rc.lds);
     return hipGetLastError();
 }
@@ -790,13 +1191,62 @@ hipError_t anal_class(const sht_plan_s *p, int c, const double *map, double2 *dt
 // Size classes (FFT length limit): 0 -> 2048, 1 -> 4096, 2 -> 8192.
 static_assert(kClassThreads[0] == 256 && kClassThreads[1] == 512 && kClassThreads[2] == 1024,
               "class thread counts must match the kernel instantiations");
+template <typename DT>
+hipError_t synth_fast_class(const sht_plan_s *p, const DT *delta, double *map, hipStream_t st)
+{
+    const RingClass &rc = p->scls[kFastClass];
+    if (rc.count == 0) return hipSuccess;
+    const size_t lds = (size_t)rc.lds.total() * sizeof(double2);
+    hipError_t e = set_lds((const void *)k_ring_synth_fast<DT>, lds);
+    if (e != hipSuccess) return e;
+    // two workgroups per CU (the LDS of a ring), a multiple of 8
+    const long long items = (long long)rc.count * p->nmaps;
+    long long grid = 2LL * (p->num_cus > 0 ? p->num_cus : 256);
+    if (grid > items) grid = items;
+    grid = ((grid + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_ring_synth_fast<DT>), dim3((unsigned)grid), dim3(kFastThreads), lds,
+                       st, rc.d_ids, rc.count, p->nmaps, p->d_rings, p->d_pool, delta,
+                       p->d_minv, p->mcontig, p->mmax, p->nm, p->nrings, map, p->npix, rc.lds);
+    return hipGetLastError();
+}
+
+template <typename DT>
+static hipError_t ring_synth_dt(const sht_plan_s *p, const DT *delta, double *map, hipStream_t st)
+{
+    hipError_t e = synth_fast_class<DT>(p, delta, map, st);
+    if (e == hipSuccess) e = synth_class<1024, 8192, DT>(p, 2, delta, map, st);
+    if (e == hipSuccess) e = synth_class<512, 4096, DT>(p, 1, delta, map, st);
+    if (e == hipSuccess) e = synth_class<256, 2048, DT>(p, 0, delta, map, st);
+    return e;
+}
+
 hipError_t launch_ring_synth(const sht_plan_s *p, const double2 *delta, double *map,
                              hipStream_t st)
 {
-    hipError_t e = synth_class<1024, 8192>(p, 2, delta, map, st);
-    if (e == hipSuccess) e = synth_class<512, 4096>(p, 1, delta, map, st);
-    if (e == hipSuccess) e = synth_class<256, 2048>(p, 0, delta, map, st);
-    return e;
+    return ring_synth_dt(p, delta, map, st);
+}
+
+hipError_t launch_ring_synth(const sht_plan_s *p, const float2 *delta, double *map,
+                             hipStream_t st)
+{
+    return ring_synth_dt(p, delta, map, st);
+}
+
+// Complex64 Delta widened to complex128 (the stage entry point's layout).
+__global__ __launch_bounds__(256) void k_widen(const float2 *__restrict__ s,
+                                               double2 *__restrict__ d, long long n)
+{
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) d[i] = make_double2((double)s[i].x, (double)s[i].y);
+}
+
+hipError_t launch_widen(const float2 *s, double2 *d, long long n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const long long nb = (n + 255) / 256;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_widen, dim3((unsigned)nb), dim3(256), 0, st, s, d, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_ring_anal(const sht_plan_s *p, const double *map, double2 *dt, hipStream_t st,
@@ -841,7 +1291,19 @@ hipError_t synth_batch_class(const BatchClass &bc, const BatchMap *maps, double 
 hipError_t launch_ring_synth_batch(const BatchClass *cls, const BatchMap *maps,
                                    double *const *outs, const void *ws, hipStream_t st)
 {
-    hipError_t e = synth_batch_class<1024, 8192>(cls[2], maps, outs, ws, st);
+    hipError_t e = hipSuccess;
+    const BatchClass &fc = cls[kFastClass];
+    if (fc.count > 0) {
+        const size_t lds = (size_t)fc.lds.total() * sizeof(double2);
+        e = set_lds((const void *)k_ring_synth_batch_fast, lds);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_ring_synth_batch_fast, dim3((unsigned)fc.count),
+                               dim3(kFastThreads), lds, st, fc.d_items, maps, outs,
+                               (const char *)ws, fc.lds);
+            e = hipGetLastError();
+        }
+    }
+    if (e == hipSuccess) e = synth_batch_class<1024, 8192>(cls[2], maps, outs, ws, st);
     if (e == hipSuccess) e = synth_batch_class<512, 4096>(cls[1], maps, outs, ws, st);
     if (e == hipSuccess) e = synth_batch_class<256, 2048>(cls[0], maps, outs, ws, st);
     return e;

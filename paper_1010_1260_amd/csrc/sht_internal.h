@@ -34,6 +34,10 @@ struct RingDesc {
     int half;         // 1: the clen-point DFT is two Bluestein DFTs of length clen / 2
                       // (even- and odd-indexed inputs) and one radix-2 step; the
                       // chirp, nb and kernel spectrum are those of length clen / 2
+    int np;           // synthesis fast path: number of Stockham passes (0: not on it)
+    int pad;
+    unsigned long long rads;  // their radices (16, 8, 4, 2, 7, 5, 3; product clen),
+                              // 5 bits each, pass p at bits 5p..5p+4
 };
 
 // One recurrence unit: a ring, or a ring and its mirror (cos negated,
@@ -65,6 +69,62 @@ struct RingClass {
 };
 constexpr int kNumRingClasses = 3;
 constexpr int kClassThreads[kNumRingClasses] = {256, 512, 1024};
+// Synthesis uses the three classes above for the rings that are not on the
+// fast path, plus one class for the fast path: even rings whose half length
+// is 7-smooth and at most kFastMaxH, run by kFastThreads-thread workgroups
+// with register-held radix-16/8/4/2/7/5/3 butterflies on a padded LDS buffer.
+constexpr int kFastClass = 3;
+constexpr int kNumSynthClasses = 4;
+constexpr int kFastThreads = 256;
+constexpr int kFastMaxH = 4096;
+constexpr int kFastMaxModes = 17 * kFastThreads;   // the fold holds m < 4352 in registers
+// padded LDS index of the fast path (one spare entry per 16)
+inline int fast_pad(int i) { return i + (i >> 4); }
+// butterflies per thread a fast pass of radix R holds in registers (at most
+// 16 complex values)
+__host__ __device__ constexpr int fast_maxq(int R)
+{
+    return R == 16 ? 1 : R == 8 ? 2 : R == 4 ? 4 : R == 2 ? 8 : R == 7 ? 2 : R == 5 ? 3 : 5;
+}
+
+// Radices of the fast path for a complex length h (1 < h <= kFastMaxH,
+// 7-smooth): as many 16s as possible, then 8, 4, 2, then 7, 5, 3.  Returns
+// the number of passes, 0 if h is not eligible (also when a pass would need
+// more butterflies per thread than fast_maxq).
+inline int fast_radices(int h, unsigned long long *rads)
+{
+    int rad[12];
+    if (h < 2 || h > kFastMaxH) return 0;
+    int np = 0, r = h;
+    while (r % 16 == 0 && np < 12) { rad[np++] = 16; r /= 16; }
+    if (r % 8 == 0 && np < 12) { rad[np++] = 8; r /= 8; }
+    if (r % 4 == 0 && np < 12) { rad[np++] = 4; r /= 4; }
+    if (r % 2 == 0 && np < 12) { rad[np++] = 2; r /= 2; }
+    for (int f : {7, 5, 3})
+        while (r % f == 0 && np < 12) { rad[np++] = f; r /= f; }
+    if (r != 1) return 0;
+    *rads = 0;
+    for (int p = 0; p < np; ++p) {
+        if (h / rad[p] > fast_maxq(rad[p]) * kFastThreads) return 0;
+        *rads |= (unsigned long long)rad[p] << (5 * p);
+    }
+    return np;
+}
+
+// Grows the fast class layout by one ring of n pixels (n even, fast path)
+// for modes 0..mmax: the padded buffer holds the phased modes, the spectrum
+// (bins 0..n/2), the alias staging of rings with fewer bins than threads and
+// the FFT; then the twiddle table.
+inline void fast_lds_add(RingLds &l, int n, int mmax)
+{
+    const int h = n / 2;
+    int top = h > kFastThreads - 1 ? h : kFastThreads - 1;
+    top = top > mmax ? top : mmax;
+    const int need = fast_pad(top) + 1;
+    l.fft_entries = l.fft_entries > need ? l.fft_entries : need;
+    const int tw = 64 + (n + 63) / 64;
+    l.tw_entries = l.tw_entries > tw ? l.tw_entries : tw;
+}
 
 // Grows the layout of class c by one ring of n pixels, Bluestein length nb
 // (0 if none) and spectrum / FFT need `need`.  A ring with fewer spectrum
@@ -75,6 +135,8 @@ inline void ring_lds_add(RingLds &l, int c, int n, int nb, int need)
     const int nt = kClassThreads[c];
     const int bins = (n % 2 == 0) ? n / 2 + 1 : n;
     if (bins < nt && need < nt) need = nt;
+    // the synthesis stages the modes in chunks of 8 nt entries
+    if (need < 8 * nt) need = 8 * nt;
     l.fft_entries = l.fft_entries > need ? l.fft_entries : need;
     const int tw = 64 + (n + 63) / 64;
     l.tw_entries = l.tw_entries > tw ? l.tw_entries : tw;
@@ -149,11 +211,14 @@ struct sht_plan_s {
     std::vector<int> ring_need;   // LDS double2 entries of each ring's spectrum / FFT
     std::vector<int> ring_n;      // pixels of each ring
     std::vector<int> ring_nb;     // Bluestein length of each ring (0: none)
-    sht::RingClass cls[sht::kNumRingClasses];
+    sht::RingClass cls[sht::kNumRingClasses];     // analysis: every ring
+    sht::RingClass scls[sht::kNumSynthClasses];   // synthesis
+    std::vector<int> ring_sclass;  // synthesis class of each ring
     int fwd_chains;      // ring pairs per lane of the FP64 forward Legendre kernel (1, 2, 4)
     int num_cus;         // compute units of the plan's device
     size_t ws_ap_bytes;  // workspace: prescaled coefficients
-    size_t ws_delta_bytes;
+    size_t ws_delta_bytes;   // workspace: forward Delta (complex64 for the mixed forms)
+    size_t ws_dt_bytes;      // workspace: adjoint Delta~ (complex128)
 };
 
 namespace sht {
@@ -174,21 +239,24 @@ hipError_t launch_legendre_adj_ws(const sht_plan_s *p, const double2 *dt, double
 size_t adj_part_bytes(const sht_plan_s *p);
 size_t mfma_bf_bytes(const sht_plan_s *p);
 hipError_t launch_prescale_f32(const sht_plan_s *p, const double *alm, float *Bf, hipStream_t st);
-hipError_t launch_legendre_mfma_f32(const sht_plan_s *p, const float *Bf, double2 *delta,
+hipError_t launch_legendre_mfma_f32(const sht_plan_s *p, const float *Bf, float2 *delta,
                                     hipStream_t st);
 size_t bf16_bytes(const sht_plan_s *p);
 hipError_t launch_prescale_bf16x3(const sht_plan_s *p, const double *alm, void *Bb,
                                   hipStream_t st);
-hipError_t launch_legendre_mfma_bf16x3(const sht_plan_s *p, const void *Bb, double2 *delta,
+hipError_t launch_legendre_mfma_bf16x3(const sht_plan_s *p, const void *Bb, float2 *delta,
                                        hipStream_t st);
 size_t f16_bytes(const sht_plan_s *p);
 int f16_super_rows();
 hipError_t launch_prescale_f16x2(const sht_plan_s *p, const double *alm, void *Bb,
                                  hipStream_t st);
-hipError_t launch_legendre_mfma_f16x2(const sht_plan_s *p, const void *Bb, double2 *delta,
+hipError_t launch_legendre_mfma_f16x2(const sht_plan_s *p, const void *Bb, float2 *delta,
                                       hipStream_t st);
 hipError_t launch_ring_synth(const sht_plan_s *p, const double2 *delta, double *map,
                              hipStream_t st);
+hipError_t launch_ring_synth(const sht_plan_s *p, const float2 *delta, double *map,
+                             hipStream_t st);
+hipError_t launch_widen(const float2 *s, double2 *d, long long n, hipStream_t st);
 hipError_t launch_ring_anal(const sht_plan_s *p, const double *map, double2 *dt, hipStream_t st,
                             const double *rw = nullptr, double cfac = 2.0);
 hipError_t launch_residual(const double *s, double *r, long long n, hipStream_t st);

@@ -109,6 +109,10 @@ void free_tables(sht_plan_s *p)
                     p->d_bm32, p->d_soff, p->d_sbm, p->d_Asb};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    for (int c = 0; c < sht::kNumSynthClasses; ++c) {
+        if (p->scls[c].d_ids) (void)hipFree(p->scls[c].d_ids);
+        p->scls[c].d_ids = nullptr;
+    }
     for (int c = 0; c < sht::kNumRingClasses; ++c) {
         if (p->cls[c].d_ids) (void)hipFree(p->cls[c].d_ids);
         p->cls[c].d_ids = nullptr;
@@ -219,29 +223,43 @@ struct PoolBuilder {
 
 }  // namespace
 
-// Prescale + Legendre stage of the forward transform into `delta`.
-static sht_status legendre_stage(sht_plan_t p, const double *alm, void *ws, double2 *delta,
+// Delta of the forward transform is complex64 in the mixed forms (the
+// precision of their FP32 parity sums) and complex128 in FP64.
+static bool delta_f32(const sht_plan_s *p) { return p->precision != SHT_FP64; }
+
+// Prescale + Legendre stage of the forward transform into `delta` (complex64
+// for the mixed forms, complex128 for FP64).
+static sht_status legendre_stage(sht_plan_t p, const double *alm, void *ws, void *delta,
                                  hipStream_t st, hipEvent_t ev_mid)
 {
     hipError_t e;
+    float2 *d32 = (float2 *)delta;
     if (p->precision == SHT_FP32_MFMA) {
         e = sht::launch_prescale_f32(p, alm, (float *)ws, st);
         if (e == hipSuccess && ev_mid) e = hipEventRecord(ev_mid, st);
-        if (e == hipSuccess) e = sht::launch_legendre_mfma_f32(p, (const float *)ws, delta, st);
+        if (e == hipSuccess) e = sht::launch_legendre_mfma_f32(p, (const float *)ws, d32, st);
     } else if (p->precision == SHT_BF16X3_MFMA) {
         e = sht::launch_prescale_bf16x3(p, alm, ws, st);
         if (e == hipSuccess && ev_mid) e = hipEventRecord(ev_mid, st);
-        if (e == hipSuccess) e = sht::launch_legendre_mfma_bf16x3(p, ws, delta, st);
+        if (e == hipSuccess) e = sht::launch_legendre_mfma_bf16x3(p, ws, d32, st);
     } else if (p->precision == SHT_F16X2_MFMA) {
         e = sht::launch_prescale_f16x2(p, alm, ws, st);
         if (e == hipSuccess && ev_mid) e = hipEventRecord(ev_mid, st);
-        if (e == hipSuccess) e = sht::launch_legendre_mfma_f16x2(p, ws, delta, st);
+        if (e == hipSuccess) e = sht::launch_legendre_mfma_f16x2(p, ws, d32, st);
     } else {
         e = sht::launch_prescale(p, alm, (double2 *)ws, st);
         if (e == hipSuccess && ev_mid) e = hipEventRecord(ev_mid, st);
-        if (e == hipSuccess) e = sht::launch_legendre_fwd(p, (const double2 *)ws, delta, st);
+        if (e == hipSuccess)
+            e = sht::launch_legendre_fwd(p, (const double2 *)ws, (double2 *)delta, st);
     }
     return e == hipSuccess ? SHT_OK : SHT_ERR_HIP;
+}
+
+// Ring synthesis of the forward transform's Delta (in the workspace).
+static hipError_t synth_stage(const sht_plan_s *p, const void *delta, double *map, hipStream_t st)
+{
+    return delta_f32(p) ? sht::launch_ring_synth(p, (const float2 *)delta, map, st)
+                        : sht::launch_ring_synth(p, (const double2 *)delta, map, st);
 }
 
 extern "C" {
@@ -316,8 +334,9 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     if (d->npix > 0) npix = d->npix;
     // ---- Fourier classification per ring
     std::vector<RingDesc> rings(R);
-    std::vector<int> ring_class(R);
+    std::vector<int> ring_class(R), ring_sclass(R);
     sht::RingLds class_lds[sht::kNumRingClasses] = {};
+    sht::RingLds sclass_lds[sht::kNumSynthClasses] = {};
     for (int r = 0; r < R; ++r) {
         const long long n = d->nphi[r];
         RingDesc &g = rings[r];
@@ -348,6 +367,15 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
         const int c = fftlen <= 2048 ? 0 : (fftlen <= 4096 ? 1 : 2);
         ring_class[r] = c;
         sht::ring_lds_add(class_lds[c], c, g.n, g.nb, need);
+        g.np = (n % 2 == 0 && g.nb == 0 && mval.back() < sht::kFastMaxModes)
+                   ? sht::fast_radices(g.clen, &g.rads) : 0;
+        if (g.np > 0) {
+            ring_sclass[r] = sht::kFastClass;
+            sht::fast_lds_add(sclass_lds[sht::kFastClass], g.n, mval.back());
+        } else {
+            ring_sclass[r] = c;
+            sht::ring_lds_add(sclass_lds[c], c, g.n, g.nb, need);
+        }
     }
 
     sht_plan_s *p = new (std::nothrow) sht_plan_s();
@@ -374,6 +402,7 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     for (int i = 0; i < d->nm; ++i) p->moff[i + 1] = p->moff[i] + (d->lmax - mval[i] + 1);
     p->nalm = p->moff.back();
     p->ring_class = ring_class;
+    p->ring_sclass = ring_sclass;
     p->ring_need.resize(R);
     p->ring_n.resize(R);
     p->ring_nb.resize(R);
@@ -514,19 +543,29 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     }
     if (st == SHT_OK) st = upload(&p->d_rings, rings, &tb);
     if (st == SHT_OK) st = upload(&p->d_pool, pb.pool, &tb);
-    for (int c = 0; c < sht::kNumRingClasses && st == SHT_OK; ++c) {
-        // longest rings first (tail balance); rings of equal length adjacent so
-        // that consecutive workgroups, which the kernels place on one XCD,
-        // share twiddle and Bluestein tables in L2
+    // longest rings first (tail balance); rings of equal length adjacent so
+    // that consecutive workgroups, which the kernels place on one XCD, share
+    // twiddle and Bluestein tables in L2
+    auto class_ids = [&](const std::vector<int> &cls_of, int c) {
         std::vector<int> ids;
         for (int r = 0; r < R; ++r)
-            if (ring_class[r] == c) ids.push_back(r);
+            if (cls_of[r] == c) ids.push_back(r);
         std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
             return d->nphi[a] > d->nphi[b];
         });
+        return ids;
+    };
+    for (int c = 0; c < sht::kNumRingClasses && st == SHT_OK; ++c) {
+        const std::vector<int> ids = class_ids(ring_class, c);
         p->cls[c].count = (int)ids.size();
         p->cls[c].lds = class_lds[c];
         st = upload(&p->cls[c].d_ids, ids, &tb);
+    }
+    for (int c = 0; c < sht::kNumSynthClasses && st == SHT_OK; ++c) {
+        const std::vector<int> ids = class_ids(ring_sclass, c);
+        p->scls[c].count = (int)ids.size();
+        p->scls[c].lds = sclass_lds[c];
+        st = upload(&p->scls[c].d_ids, ids, &tb);
     }
     if (st == SHT_OK && !prep_ids.empty()) {
         int *d_ids = nullptr;
@@ -553,7 +592,10 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
         : p->precision == SHT_F16X2_MFMA  ? sht::f16_bytes(p)
                                           : (size_t)p->nmaps * (size_t)p->nalm * sizeof(double2),
         256);
-    p->ws_delta_bytes = align_up((size_t)p->nmaps * (size_t)R * (size_t)p->nm * sizeof(double2), 256);
+    p->ws_dt_bytes = align_up((size_t)p->nmaps * (size_t)R * (size_t)p->nm * sizeof(double2), 256);
+    p->ws_delta_bytes = align_up((size_t)p->nmaps * (size_t)R * (size_t)p->nm *
+                                     (delta_f32(p) ? sizeof(float2) : sizeof(double2)),
+                                 256);
     p->fwd_chains = default_fwd_chains(p);
     p->magic = sht::kPlanMagic;
     *out = p;
@@ -579,7 +621,7 @@ static size_t fwd_workspace_bytes(const sht_plan_s *p)
 static size_t workspace_bytes(const sht_plan_s *p)
 {
     const size_t fwd = fwd_workspace_bytes(p);
-    const size_t adj = p->ws_delta_bytes + align_up(sht::adj_part_bytes(p), 256);
+    const size_t adj = p->ws_dt_bytes + align_up(sht::adj_part_bytes(p), 256);
     return std::max(fwd, adj);
 }
 
@@ -616,8 +658,19 @@ sht_status sht_alm2delta(sht_plan_t p, const double *alm, double *delta, void *w
     sht_status s = check_plan(p);
     if (s != SHT_OK) return s;
     if (!alm || !delta) return SHT_ERR_INVALID_ARG;
-    if (!ws || ws_bytes < p->ws_ap_bytes) return SHT_ERR_WORKSPACE;
-    return legendre_stage(p, alm, ws, (double2 *)delta, (hipStream_t)stream, nullptr);
+    if (!delta_f32(p)) {
+        if (!ws || ws_bytes < p->ws_ap_bytes) return SHT_ERR_WORKSPACE;
+        return legendre_stage(p, alm, ws, delta, (hipStream_t)stream, nullptr);
+    }
+    // mixed forms: complex64 Delta in the workspace, widened into the caller's buffer
+    if (!ws || ws_bytes < fwd_workspace_bytes(p)) return SHT_ERR_WORKSPACE;
+    float2 *d32 = (float2 *)((char *)ws + p->ws_ap_bytes);
+    s = legendre_stage(p, alm, ws, d32, (hipStream_t)stream, nullptr);
+    if (s == SHT_OK)
+        s = from_hip(sht::launch_widen(d32, (double2 *)delta,
+                                       (long long)p->nmaps * p->nm * p->nrings,
+                                       (hipStream_t)stream));
+    return s;
 }
 
 sht_status sht_delta2map(sht_plan_t p, const double *delta, double *map, void *stream)
@@ -636,9 +689,9 @@ sht_status sht_alm2map(sht_plan_t p, const double *alm, double *map, void *ws, s
     if (!alm || !map) return SHT_ERR_INVALID_ARG;
     if (!ws || ws_bytes < fwd_workspace_bytes(p)) return SHT_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
-    double2 *delta = (double2 *)((char *)ws + p->ws_ap_bytes);
+    void *delta = (char *)ws + p->ws_ap_bytes;
     s = legendre_stage(p, alm, ws, delta, st, nullptr);
-    if (s == SHT_OK) s = from_hip(sht::launch_ring_synth(p, delta, map, st));
+    if (s == SHT_OK) s = from_hip(synth_stage(p, delta, map, st));
     return s;
 }
 
@@ -733,11 +786,11 @@ sht_status sht_alm2map_events(sht_plan_t p, const double *alm, double *map, void
         if (!events[k]) return SHT_ERR_INVALID_ARG;
     if (!ws || ws_bytes < fwd_workspace_bytes(p)) return SHT_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
-    double2 *delta = (double2 *)((char *)ws + p->ws_ap_bytes);
+    void *delta = (char *)ws + p->ws_ap_bytes;
     s = from_hip(hipEventRecord((hipEvent_t)events[0], st));
     if (s == SHT_OK) s = legendre_stage(p, alm, ws, delta, st, (hipEvent_t)events[1]);
     if (s == SHT_OK) s = from_hip(hipEventRecord((hipEvent_t)events[2], st));
-    if (s == SHT_OK) s = from_hip(sht::launch_ring_synth(p, delta, map, st));
+    if (s == SHT_OK) s = from_hip(synth_stage(p, delta, map, st));
     if (s == SHT_OK) s = from_hip(hipEventRecord((hipEvent_t)events[3], st));
     return s;
 }
@@ -770,7 +823,7 @@ sht_status sht_alm2map_adjoint(sht_plan_t p, const double *map, double *alm, voi
     if (!ws || ws_bytes < workspace_bytes(p)) return SHT_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     double2 *dt = (double2 *)ws;
-    double2 *part = (double2 *)((char *)ws + p->ws_delta_bytes);
+    double2 *part = (double2 *)((char *)ws + p->ws_dt_bytes);
     s = from_hip(sht::launch_ring_anal(p, map, dt, st));
     if (s == SHT_OK) s = from_hip(sht::launch_legendre_adj_ws(p, dt, part, alm, st));
     return s;
@@ -787,15 +840,15 @@ sht_status sht_map2alm(sht_plan_t p, const double *map, const double *ring_weigh
     if (!ws || ws_bytes < workspace_bytes(p)) return SHT_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     double2 *dt = (double2 *)ws;
-    double2 *part = (double2 *)((char *)ws + p->ws_delta_bytes);
-    double2 *delta = (double2 *)((char *)ws + p->ws_ap_bytes);
+    double2 *part = (double2 *)((char *)ws + p->ws_dt_bytes);
+    void *delta = (char *)ws + p->ws_ap_bytes;
     // a = D adjoint(w s): the analysis with c_m = 1 for every m
     s = from_hip(sht::launch_ring_anal(p, map, dt, st, ring_weight, 1.0));
     if (s == SHT_OK) s = from_hip(sht::launch_legendre_adj_ws(p, dt, part, alm, st, false));
     // a <- a + D adjoint(w (s - alm2map(a)))
     for (int it = 0; it < niter && s == SHT_OK; ++it) {
         s = legendre_stage(p, alm, ws, delta, st, nullptr);
-        if (s == SHT_OK) s = from_hip(sht::launch_ring_synth(p, delta, tmp_map, st));
+        if (s == SHT_OK) s = from_hip(synth_stage(p, delta, tmp_map, st));
         if (s == SHT_OK)
             s = from_hip(sht::launch_residual(map, tmp_map, (long long)p->nmaps * p->npix, st));
         if (s == SHT_OK) s = from_hip(sht::launch_ring_anal(p, tmp_map, dt, st, ring_weight, 1.0));

@@ -122,9 +122,9 @@ def test_stale_error_of_the_caller_is_not_reported(P):
 
 
 def test_forward_workspace_suffices_for_synthesis(P):
-    """Synthesis runs in forward_workspace_bytes; the adjoint, which also
-    keeps partial sums per block of 256 ring pairs, asks for more once there
-    are several blocks (320 ring pairs at nside 160: two)."""
+    """Synthesis runs in forward_workspace_bytes and refuses one byte less;
+    workspace_bytes covers every call (the adjoint also keeps partial sums
+    per block of 256 ring pairs) and the adjoint refuses one byte less."""
     import ctypes
     from paper_1010_1260_amd import _lib as L
     _say("forward-only workspace")
@@ -132,7 +132,8 @@ def test_forward_workspace_suffices_for_synthesis(P):
     g = W.healpix_geometry(nside)
     plan = P.Plan(lmax, g, nmaps=nmaps)
     fwd = int(plan.info.forward_workspace_bytes)
-    assert 0 < fwd < plan.workspace_bytes
+    full = int(plan.workspace_bytes)
+    assert 0 < fwd <= full
     alms = np.stack([W.random_alm(lmax, [604, i]) for i in range(nmaps)])
     a = torch.from_numpy(alms).to(_dev())
     ws = torch.empty(fwd, dtype=torch.uint8, device=_dev())
@@ -145,8 +146,9 @@ def test_forward_workspace_suffices_for_synthesis(P):
     assert lib.sht_alm2map(plan.handle, vp(a.data_ptr()), vp(out.data_ptr()), vp(ws.data_ptr()),
                            fwd - 1, st) == L.SHT_ERR_WORKSPACE
     adj = torch.empty((nmaps, plan.nalm), dtype=torch.complex128, device=_dev())
+    wsf = torch.empty(full, dtype=torch.uint8, device=_dev())
     assert lib.sht_alm2map_adjoint(plan.handle, vp(out.data_ptr()), vp(adj.data_ptr()),
-                                   vp(ws.data_ptr()), fwd, st) == L.SHT_ERR_WORKSPACE
+                                   vp(wsf.data_ptr()), full - 1, st) == L.SHT_ERR_WORKSPACE
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     for i in range(nmaps):
