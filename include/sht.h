@@ -226,6 +226,20 @@ sht_status sht_alm2map_events(sht_plan_t plan, const double *alm, double *map,
 sht_status sht_alm2map_adjoint(sht_plan_t plan, const double *map, double *alm,
                                void *ws, size_t ws_bytes, void *stream);
 
+/* alm2map for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same transform and kernels as sht_alm2map, with the workspace taken from a
+ * device array of SHT_NOALLOC_SCRATCH_BYTES that the library holds on each
+ * device until the process ends (its address is looked up on the first call
+ * on a device).  Calls nothing that allocates.  Returns SHT_ERR_WORKSPACE when
+ * sht_plan_info.forward_workspace_bytes exceeds SHT_NOALLOC_SCRATCH_BYTES.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (different streams, or host threads) race and must be
+ * serialised by the caller.  The array's contents on entry are ignored (no
+ * part of it needs to start at zero). */
+#define SHT_NOALLOC_SCRATCH_BYTES (64u << 20)
+sht_status sht_alm2map_noalloc(sht_plan_t plan, const double *alm, double *map, void *stream);
+
 /* The two stages on their own (same kernels as sht_alm2map).
  * delta: device complex128 [nmaps][nm][nrings], Delta_m(theta_r) of
  * Eq. (DeltaDef) for the i-th m of the set at [b][i][r] (rings contiguous:

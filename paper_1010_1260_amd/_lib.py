@@ -26,6 +26,7 @@ SHT_BF16X3_MFMA = 2
 SHT_F16X2_MFMA = 3
 SHT_FLAG_NO_PAIRING = 1
 
+SHT_NOALLOC_SCRATCH_BYTES = 64 << 20
 SHT_MAX_LMAX = 16383
 SHT_MAX_NPHI = 16384
 
@@ -37,7 +38,7 @@ EXPORTED = [
     "sht_version",
     "sht_plan_batch", "sht_batch_destroy", "sht_batch_workspace_size", "sht_alm2map_batch",
     "sht_batch_get_config", "sht_batch_set_config", "sht_batch_autotune",
-    "sht_batch_graph_capture", "sht_batch_graph_launch",
+    "sht_batch_graph_capture", "sht_batch_graph_launch", "sht_alm2map_noalloc",
 ]
 
 
@@ -112,6 +113,7 @@ def load(path: str | None = None):
     L.sht_alm2map_events.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp,
                                      ctypes.POINTER(ctypes.c_void_p)]
     L.sht_alm2map_adjoint.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.sht_alm2map_noalloc.argtypes = [vp, vp, vp, vp]
     L.sht_alm2delta.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp]
     L.sht_delta2map.argtypes = [vp, vp, vp, vp]
     L.sht_map2delta_adjoint.argtypes = [vp, vp, vp, vp]
@@ -122,6 +124,7 @@ def load(path: str | None = None):
     L.sht_plan_autotune.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_char_p, vp]
     for fn in ["sht_plan", "sht_plan_destroy", "sht_plan_get_info", "sht_plan_workspace_size",
                "sht_alm2map", "sht_alm2map_events", "sht_alm2map_adjoint", "sht_alm2delta", "sht_delta2map",
+               "sht_alm2map_noalloc",
                "sht_map2delta_adjoint", "sht_delta2alm_adjoint", "sht_map2alm",
                "sht_plan_get_config", "sht_plan_set_config", "sht_plan_autotune"]:
         getattr(L, fn).restype = ctypes.c_int

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsht.so")
-SOURCES = ["sht_plan.cpp", "batch.cpp", "legendre.hip", "legendre_mfma.hip", "legendre_bf16.hip", "legendre_f16.hip", "ringfft.hip"]
+SOURCES = ["sht_plan.cpp", "batch.cpp", "legendre.hip", "legendre_mfma.hip", "legendre_bf16.hip", "legendre_f16.hip", "ringfft.hip", "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

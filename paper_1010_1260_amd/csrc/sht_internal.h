@@ -266,6 +266,12 @@ hipError_t launch_batch_legendre(const BatchMap *maps, int nmaps, long long max_
                                  hipStream_t st);
 hipError_t launch_ring_synth_batch(const BatchClass *cls, const BatchMap *maps,
                                    double *const *outs, const void *ws, hipStream_t st);
+// The forward transform of a plan into a caller workspace of at least
+// forward_workspace(p) bytes (no checks: the entry points validate).
+size_t forward_workspace(const sht_plan_s *p);
+sht_status check_plan_device(sht_plan_t p);
+sht_status forward_transform(sht_plan_t p, const double *alm, double *map, void *ws,
+                             hipStream_t st);
 // Plan time: spectra of the Bluestein chirp kernels.
 hipError_t launch_bluestein_prep(const sht_plan_s *p, const int *ring_ids, int nids,
                                  hipStream_t st);

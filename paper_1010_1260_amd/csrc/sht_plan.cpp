@@ -681,6 +681,27 @@ sht_status sht_delta2map(sht_plan_t p, const double *delta, double *map, void *s
     return from_hip(sht::launch_ring_synth(p, (const double2 *)delta, map, (hipStream_t)stream));
 }
 
+}  // extern "C"
+
+namespace sht {
+
+size_t forward_workspace(const sht_plan_s *p) { return fwd_workspace_bytes(p); }
+
+sht_status check_plan_device(sht_plan_t p) { return check_plan(p); }
+
+sht_status forward_transform(sht_plan_t p, const double *alm, double *map, void *ws,
+                             hipStream_t st)
+{
+    void *delta = (char *)ws + p->ws_ap_bytes;
+    sht_status s = legendre_stage(p, alm, ws, delta, st, nullptr);
+    if (s == SHT_OK) s = from_hip(synth_stage(p, delta, map, st));
+    return s;
+}
+
+}  // namespace sht
+
+extern "C" {
+
 sht_status sht_alm2map(sht_plan_t p, const double *alm, double *map, void *ws, size_t ws_bytes,
                        void *stream)
 {
@@ -688,11 +709,7 @@ sht_status sht_alm2map(sht_plan_t p, const double *alm, double *map, void *ws, s
     if (s != SHT_OK) return s;
     if (!alm || !map) return SHT_ERR_INVALID_ARG;
     if (!ws || ws_bytes < fwd_workspace_bytes(p)) return SHT_ERR_WORKSPACE;
-    hipStream_t st = (hipStream_t)stream;
-    void *delta = (char *)ws + p->ws_ap_bytes;
-    s = legendre_stage(p, alm, ws, delta, st, nullptr);
-    if (s == SHT_OK) s = from_hip(synth_stage(p, delta, map, st));
-    return s;
+    return sht::forward_transform(p, alm, map, ws, (hipStream_t)stream);
 }
 
 sht_status sht_plan_get_config(sht_plan_t p, int32_t *chains)
