@@ -88,9 +88,11 @@ typedef enum {
 } sht_precision;
 
 #define SHT_MAX_LMAX 16383
-/* largest ring the per-ring Fourier kernels hold in LDS:
- * even nphi: nphi/2 <= 8192 if nphi/2 factors into 2,3,5,7, else nphi/2 <= 4096;
- * odd nphi: nphi <= 8192 if it factors into 3,5,7, else nphi <= 4096. */
+/* largest ring the per-ring Fourier kernels hold in LDS.  With h = nphi/2:
+ * even nphi: h <= 8192, and h even, or h a product of 3, 5, 7, or h <= 4096;
+ * odd nphi: nphi <= 8192, and nphi a product of 3, 5, 7, or nphi <= 4096.
+ * sht_plan returns SHT_ERR_UNSUPPORTED for any other ring (16382 and 8191,
+ * say).  Every HEALPix ring up to nside 4096 is supported. */
 #define SHT_MAX_NPHI 16384
 
 /* Geometry and problem description for sht_plan.  All pointers are host

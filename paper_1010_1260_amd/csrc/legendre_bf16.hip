@@ -330,8 +330,8 @@ struct MState {
 // Seed and phase 1 (recurrence alone while the whole workgroup is below
 // 2^-400), then the register copy of the first live super-block.
 __device__ void m_begin(MState &st, SuperStage &g, int i, const int *__restrict__ mval,
-                        const long long *__restrict__ moff, const long long *__restrict__ boff,
-                        const double *__restrict__ mu, int lmax, const double *__restrict__ A,
+                        const long long *__restrict__ soff, const long long *__restrict__ boff,
+                        const double *__restrict__ mu, int lmax, const double *__restrict__ Asb,
                         const v4u *__restrict__ Bg, double x, double s, int tid)
 {
     st.i = i;
@@ -339,7 +339,10 @@ __device__ void m_begin(MState &st, SuperStage &g, int i, const int *__restrict_
     st.len = lmax - st.m + 1;
     st.nblk = (st.len + kBlkSteps - 1) / kBlkSteps;
     st.nsb = (st.nblk + kSuper - 1) / kSuper;
-    st.Am = A + moff[i];
+    // coefficients from the per-super-block copy, zero past the m's last row:
+    // the copies of a super-block run past the m's end, and with A = 0 there
+    // the recurrence of the unused rows stays bounded (u_l = -u_{l-2})
+    st.Am = Asb + soff[i] * kSuperRows;
     st.Bm = Bg + boff[i] * kBlkElems;
     st.ub = 0.0;
     seed_mm(mu[i], s, st.m, st.ua, st.k);
@@ -401,9 +404,9 @@ __device__ __forceinline__ void m_compute(MState &st, char *ldsA, char *ldsB, do
 
 __global__ __launch_bounds__(kThreads, 2) void k_legendre_mfma_bf16x3(
     const PairDesc *__restrict__ pairs, int npairs, int pgroups,
-    const int *__restrict__ mval, const long long *__restrict__ moff,
+    const int *__restrict__ mval, const long long *__restrict__ soff,
     const long long *__restrict__ boff, const double *__restrict__ mu, int nm, int nmpairs,
-    int lmax, const double *__restrict__ A, const v4u *__restrict__ Bb, long long nblocks,
+    int lmax, const double *__restrict__ Asb, const v4u *__restrict__ Bb, long long nblocks,
     float2 *__restrict__ delta, int nrings, int nmaps, long long total)
 {
     __shared__ __attribute__((aligned(16))) char ldsA[kBufBytes];
@@ -425,13 +428,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_legendre_mfma_bf16x3(
     MState st;
     SuperStage g;
     MfmaTiles tot;
-    m_begin(st, g, q, mval, moff, boff, mu, lmax, A, Bg, x, s, tid);
+    m_begin(st, g, q, mval, soff, boff, mu, lmax, Asb, Bg, x, s, tid);
     m_commit(st, g, ldsA, tid);
     m_compute(st, ldsA, ldsB, x, tid, tot);
     const int i1 = st.i;
     const int i2 = nm - 1 - q;
     const bool two = i2 != q;
-    if (two) m_begin(st, g, i2, mval, moff, boff, mu, lmax, A, Bg, x, s, tid);
+    if (two) m_begin(st, g, i2, mval, soff, boff, mu, lmax, Asb, Bg, x, s, tid);
     m_store(tot, i1, delta, pairs, npairs, pb, grp, nmaps, nrings, nm, tid & 63);
     if (two) {
         m_commit(st, g, ldsA, tid);
@@ -479,10 +482,12 @@ hipError_t launch_legendre_mfma_bf16x3(const sht_plan_s *p, const void *Bb, floa
     const int nmpairs = (p->nm + 1) / 2;
     const int groups = (p->nmaps + 15) / 16;
     const long long total = (long long)pgroups * nmpairs * groups;
+    // the plan's zero-padded coefficient copy has the super-block length of this kernel
+    if (f16_super_rows() != kSuperRows) return hipErrorInvalidConfiguration;
     if (total <= 0 || total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_legendre_mfma_bf16x3, dim3((unsigned)total), dim3(kThreads), 0, st,
-                       p->d_pairs, p->npairs, pgroups, p->d_mval, p->d_moff, p->d_boff, p->d_mu, p->nm,
-                       nmpairs, p->lmax, p->d_A, reinterpret_cast<const v4u *>(Bb),
+                       p->d_pairs, p->npairs, pgroups, p->d_mval, p->d_soff, p->d_boff, p->d_mu, p->nm,
+                       nmpairs, p->lmax, p->d_Asb, reinterpret_cast<const v4u *>(Bb),
                        bf16_blocks(p), delta, p->nrings, p->nmaps,
                        total);
     return hipGetLastError();

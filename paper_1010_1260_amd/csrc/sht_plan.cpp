@@ -516,10 +516,10 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
             st = upload(&p->d_bm16, bm16, &tb);
         }
     }
-    if (st == SHT_OK && p->precision == SHT_F16X2_MFMA) {
-        // split-FP16 form: super-blocks of 128 rows per m, and the
-        // recurrence coefficients copied per super-block with zeros past each
-        // m's last row
+    if (st == SHT_OK && p->precision != SHT_FP64) {
+        // mixed forms: super-blocks of 128 rows per m, and the recurrence
+        // coefficients copied per super-block with zeros past each m's last
+        // row (the kernels' super-block copies run past an m's end)
         const int SR = sht::f16_super_rows();
         std::vector<long long> soff(d->nm);
         long long acc_s = 0;
