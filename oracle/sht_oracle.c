@@ -33,10 +33,13 @@
  * by 2^(S k) before it is used.  The rescale "table" of the paper is here
  * the set of powers 2^(S k).
  *
- * Loop order is that of Algorithm 1: ring, then m, then l.  The rings are
- * independent, so they are spread over OpenMP threads; that changes no
- * arithmetic.  Build with -ffp-contract=off so that every expression is
- * evaluated as written.
+ * Structure: plm_column evaluates the column P_lm(x), l = m..lmax, of one
+ * m at one colatitude from the seed and the recurrence; Delta_m is then the
+ * dot product of that column with the a_lm of the m (Eq. DeltaDef), and the
+ * adjoint adds the column times a ring's Delta~_m into the coefficients.
+ * Rings (forward) or m (adjoint) are independent and are spread over OpenMP
+ * threads, which changes no arithmetic.  Build with -ffp-contract=off so that
+ * every expression is evaluated as written.
  */
 #include <math.h>
 #include <stdint.h>
@@ -96,35 +99,54 @@ static void seed_mm(double mu, double s, int m, double *v, int *k)
     *k = (int)kk;
 }
 
+/* The column P_lm(x), l = m..lmax, of one m at one point (x = cos theta,
+ * s = sin theta): P[l - m] for l = m..lmax.  mu_m is the seed constant of
+ * Eq. (pmm); b[l - m] = beta_{l,m} of Eq. (betaDef) for l = m+1..lmax.  The
+ * values are carried as v 2^(S k) (seed_mm) through the recurrence of
+ * Eq. (assLegRec) and the start of Eq. (pm1m); whenever |v_l| passes 2^S the
+ * last two values are scaled by 2^-S and k grows by one (Sec. 2.2.2).  Each
+ * P_lm is returned as v 2^(S k), which is 0 for values below about 2^-1074. */
+static void plm_column(int lmax, int m, double x, double s, double mu_m, const double *b,
+                       double *P)
+{
+    double v0, v1;
+    int k;
+    seed_mm(mu_m, s, m, &v0, &k);
+    double scale = ldexp(1.0, ORACLE_S * k);
+    P[0] = v0 * scale;
+    if (m + 1 > lmax) return;
+    v1 = b[1] * x * v0;
+    P[1] = v1 * scale;
+    for (int l = m + 2; l <= lmax; ++l) {
+        const int j = l - m;
+        double v2 = b[j] * (x * v1 - v0 / b[j - 1]);
+        if (fabs(v2) > 0x1p256) {
+            v2 = ldexp(v2, -ORACLE_S);
+            v1 = ldexp(v1, -ORACLE_S);
+            k += 1;
+            scale = ldexp(1.0, ORACLE_S * k);
+        }
+        P[j] = v2 * scale;
+        v0 = v1;
+        v1 = v2;
+    }
+}
+
 /* P_lm(x) for l = 0..lmax at one point (x = cos theta, s = sin theta);
  * entries with l < m are set to 0.  Returns 0 on success. */
 int oracle_lambda(int lmax, int m, double x, double s, double *out)
 {
     if (lmax < 0 || m < 0 || m > lmax) return -1;
     double *mu = (double *)malloc(sizeof(double) * (size_t)(m + 1));
-    if (!mu) return -2;
+    double *b = (double *)malloc(sizeof(double) * (size_t)(lmax - m + 1));
+    if (!mu || !b) { free(mu); free(b); return -2; }
     oracle_mu(m, mu);
+    b[0] = 0.0;
+    for (int l = m + 1; l <= lmax; ++l) b[l - m] = beta(l, m);
     for (int l = 0; l < m; ++l) out[l] = 0.0;
-    double v0, v1; int k;
-    seed_mm(mu[m], s, m, &v0, &k);
-    double scale = ldexp(1.0, ORACLE_S * k);
-    out[m] = v0 * scale;
-    if (m + 1 <= lmax) {
-        v1 = sqrt(2.0 * m + 3.0) * x * v0; /* Eq. (pm1m), beta_{m+1,m} */
-        out[m + 1] = v1 * scale;
-        for (int l = m + 2; l <= lmax; ++l) {
-            double v2 = beta(l, m) * (x * v1 - v0 / beta(l - 1, m));
-            if (fabs(v2) > 0x1p256) {
-                v2 = ldexp(v2, -ORACLE_S);
-                v1 = ldexp(v1, -ORACLE_S);
-                k += 1;
-                scale = ldexp(1.0, ORACLE_S * k);
-            }
-            out[l] = v2 * scale;
-            v0 = v1; v1 = v2;
-        }
-    }
+    plm_column(lmax, m, x, s, mu[m], b, out + m);
     free(mu);
+    free(b);
     return 0;
 }
 
@@ -139,9 +161,8 @@ static int64_t *alm_offsets(int lmax, int nm, const int32_t *mval)
     return off;
 }
 
-/* Per-m beta tables, precomputed once as in Algorithm 2 ("precompute the
- * recurrence coefficients beta_lm for fixed m"); the same numbers for
- * every ring. */
+/* beta_{l,m} of every m of the set, computed once (the same numbers serve
+ * every ring), in the packed m-major layout of the coefficients. */
 static double *beta_tables(int lmax, int nm, const int32_t *mval, const int64_t *off)
 {
     double *b = (double *)malloc(sizeof(double) * (size_t)off[nm]);
@@ -164,8 +185,9 @@ static int check_mset(int lmax, int nm, const int32_t *mval)
     return 0;
 }
 
-/* Delta_m(r) for every ring r and every m of the set (Eq. DeltaDef),
- * Algorithm 1 with Algorithm 2 merged into it.
+/* Delta_m(r) for every ring r and every m of the set (Eq. DeltaDef): the
+ * dot product of the column P_lm(cos theta_r), l = m..lmax, with the a_lm
+ * of the m (only the real part of a_l0 enters).
  *   alm   : complex [nalm] interleaved (re, im), m-major packed
  *   delta : complex [nrings][nm] interleaved, written
  * nthreads <= 0 uses the OpenMP default. */
@@ -179,49 +201,31 @@ int oracle_delta(int lmax, int nm, const int32_t *mval, int nrings,
     double *bt = off ? beta_tables(lmax, nm, mval, off) : NULL;
     if (!off || !mu || !bt) { free(off); free(mu); free(bt); return -2; }
     oracle_mu(lmax, mu);
+    int fail = 0;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 1)
 #endif
-    for (int r = 0; r < nrings; ++r) {               /* every ring */
-        const double x = cth[r], s = sth[r];
-        for (int i = 0; i < nm; ++i) {               /* every m */
+    for (int r = 0; r < nrings; ++r) {
+        double *P = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
+        if (!P) { fail = 1; continue; }
+        for (int i = 0; i < nm; ++i) {
             const int m = mval[i];
-            const double *a = alm + 2 * off[i];      /* a_{l m}, l = m.. */
-            const double *b = bt + off[i];           /* beta_{l m}, l = m.. */
-            double v0, v1; int k;
-            seed_mm(mu[m], s, m, &v0, &k);
-            double scale = ldexp(1.0, ORACLE_S * k);
-            double dre = 0.0, dim = 0.0, p;
-            p = v0 * scale;                          /* P_mm */
-            dre += a[0] * p;
-            if (m > 0) dim += a[1] * p;
-            if (m + 1 <= lmax) {
-                v1 = b[1] * x * v0;                  /* P_{m+1,m}, Eq. (pm1m) */
-                p = v1 * scale;
-                dre += a[2] * p;
-                if (m > 0) dim += a[3] * p;
-                for (int l = m + 2; l <= lmax; ++l) {   /* every l */
-                    const int j = l - m;
-                    double v2 = b[j] * (x * v1 - v0 / b[j - 1]);
-                    if (fabs(v2) > 0x1p256) {        /* test / rescale */
-                        v2 = ldexp(v2, -ORACLE_S);
-                        v1 = ldexp(v1, -ORACLE_S);
-                        k += 1;
-                        scale = ldexp(1.0, ORACLE_S * k);
-                    }
-                    p = v2 * scale;                  /* scale back before use */
-                    dre += a[2 * j] * p;
-                    if (m > 0) dim += a[2 * j + 1] * p;
-                    v0 = v1; v1 = v2;
-                }
+            const int len = lmax - m + 1;
+            const double *a = alm + 2 * off[i];
+            plm_column(lmax, m, cth[r], sth[r], mu[m], bt + off[i], P);
+            double dre = 0.0, dim = 0.0;
+            for (int j = 0; j < len; ++j) {
+                dre += a[2 * j] * P[j];
+                if (m > 0) dim += a[2 * j + 1] * P[j];
             }
             delta[2 * ((int64_t)r * nm + i)] = dre;
             delta[2 * ((int64_t)r * nm + i) + 1] = dim;
         }
+        free(P);
     }
     free(off); free(mu); free(bt);
-    return 0;
+    return fail ? -2 : 0;
 }
 
 /* Transposed Legendre stage of the adjoint transform:
@@ -242,47 +246,32 @@ int oracle_delta_adjoint(int lmax, int nm, const int32_t *mval, int nrings,
     if (!off || !mu || !bt) { free(off); free(mu); free(bt); return -2; }
     oracle_mu(lmax, mu);
     memset(out, 0, sizeof(double) * 2 * (size_t)off[nm]);
+    int fail = 0;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 1)
 #endif
     for (int i = 0; i < nm; ++i) {
         const int m = mval[i];
+        const int len = lmax - m + 1;
         double *o = out + 2 * off[i];
-        const double *b = bt + off[i];
+        double *P = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
+        if (!P) { fail = 1; continue; }
         for (int r = 0; r < nrings; ++r) {
-            const double x = cth[r], s = sth[r];
             const double gre = dt[2 * ((int64_t)r * nm + i)];
             const double gim = dt[2 * ((int64_t)r * nm + i) + 1];
-            double v0, v1; int k;
-            seed_mm(mu[m], s, m, &v0, &k);
-            double scale = ldexp(1.0, ORACLE_S * k);
-            double p = v0 * scale;
-            o[0] += p * gre; o[1] += p * gim;
-            if (m + 1 <= lmax) {
-                v1 = b[1] * x * v0;
-                p = v1 * scale;
-                o[2] += p * gre; o[3] += p * gim;
-                for (int l = m + 2; l <= lmax; ++l) {
-                    const int j = l - m;
-                    double v2 = b[j] * (x * v1 - v0 / b[j - 1]);
-                    if (fabs(v2) > 0x1p256) {
-                        v2 = ldexp(v2, -ORACLE_S);
-                        v1 = ldexp(v1, -ORACLE_S);
-                        k += 1;
-                        scale = ldexp(1.0, ORACLE_S * k);
-                    }
-                    p = v2 * scale;
-                    o[2 * j] += p * gre; o[2 * j + 1] += p * gim;
-                    v0 = v1; v1 = v2;
-                }
+            plm_column(lmax, m, cth[r], sth[r], mu[m], bt + off[i], P);
+            for (int j = 0; j < len; ++j) {
+                o[2 * j] += P[j] * gre;
+                o[2 * j + 1] += P[j] * gim;
             }
         }
         if (m == 0)
             for (int l = 0; l <= lmax; ++l) o[2 * l + 1] = 0.0;
+        free(P);
     }
     free(off); free(mu); free(bt);
-    return 0;
+    return fail ? -2 : 0;
 }
 
 int oracle_max_threads(void)

@@ -19,21 +19,17 @@ SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
 
 MUTATIONS = {
     # recurrence sign as printed in Eq. (assLegRec)
-    "recurrence_plus": [("(x * v1 - v0 / b[j - 1])", "(x * v1 + v0 / b[j - 1])"),
-                        ("(x * v1 - v0 / beta(l - 1, m))", "(x * v1 + v0 / beta(l - 1, m))")],
+    "recurrence_plus": [("(x * v1 - v0 / b[j - 1])", "(x * v1 + v0 / b[j - 1])")],
     # seed exponent m instead of m/2 (Eq. pmm as printed): s^(2m)
     "seed_exponent_m": [("int p = m;", "int p = 2 * m;")],
     # second seed with the wrong beta index (Eq. pm1m)
-    "pm1m_index": [("v1 = b[1] * x * v0;", "v1 = b[2] * x * v0;"),
-                   ("v1 = sqrt(2.0 * m + 3.0) * x * v0;", "v1 = sqrt(2.0 * m + 5.0) * x * v0;")],
+    "pm1m_index": [("v1 = b[1] * x * v0;", "v1 = b[2] * x * v0;")],
     # mu_m running product off by one
     "mu_ratio": [("sqrt((2.0 * m + 1.0) / (2.0 * m))", "sqrt((2.0 * m + 2.0) / (2.0 * m))")],
     # rescale bookkeeping: exponent not advanced (value scaled back wrongly)
-    "rescale_exponent": [("                k += 1;\n                scale", "                k += 0;\n                scale"),
-                         ("                        k += 1;\n                        scale",
-                          "                        k += 0;\n                        scale")],
+    "rescale_exponent": [("            k += 1;\n            scale", "            k += 0;\n            scale")],
     # dropped conjugate-symmetric half: imaginary part of a_lm ignored
-    "drop_imag": [("if (m > 0) dim += a[2 * j + 1] * p;", "if (m > 0) dim += 0.0 * p;")],
+    "drop_imag": [("if (m > 0) dim += a[2 * j + 1] * P[j];", "if (m > 0) dim += 0.0 * P[j];")],
 }
 
 
