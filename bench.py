@@ -232,6 +232,75 @@ def run_small(torch, np, W, dev, reps=200):
             "rel_err_vs_oracle": float(np.linalg.norm(got - exp) / np.linalg.norm(exp))}
 
 
+def _time_calls(fn, torch, reps=5, warm=2):
+    """Median of `reps` timed calls of fn (HIP events on the current stream)."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def shape_sweep(torch, np, W, dev):
+    """Launch shapes over sizes (the source of the libraries' default tables):
+    the FP64 forward Legendre kernel's ring pairs per lane {1, 2, 4} on HEALPix
+    grids (nside = l_max / 2, Legendre stage only), and the batch's (chains per
+    lane, persistent waves per CU) on batches of uniform and uneven l_max.
+    Prints one JSON line."""
+    from paper_1010_1260_amd import Batch, Plan
+    ncu = torch.cuda.get_device_properties(dev).multi_processor_count
+    fwd = []
+    for L, nm in [(64, 1), (64, 16), (128, 1), (128, 16), (256, 1), (256, 4), (256, 16),
+                  (512, 1), (512, 4), (512, 16), (1024, 1), (1024, 4), (1024, 16),
+                  (2048, 1), (2048, 4), (4096, 1)]:
+        g = W.healpix_geometry(L // 2)
+        plan = Plan(L, g, nmaps=nm, device=dev)
+        a = torch.from_numpy(np.stack([W.random_alm(L, [9, i]) for i in range(nm)])).to(dev)
+        waves1 = ((plan.npairs + 63) // 64) * ((plan.nm + 1) // 2) * nm / ncu
+        default = plan.config
+        ms = {}
+        for ch in (1, 2, 4):
+            plan.set_config(ch)
+            ms[ch] = _time_calls(lambda: plan.alm2delta(a), torch)
+        fwd.append({"lmax": L, "nside": L // 2, "maps": nm, "waves_per_cu_at_1": waves1,
+                    "ms": ms, "fastest": min(ms, key=ms.get), "default": default})
+        del plan, a
+    batches = {"uniform 128 x4": [128] * 4, "uniform 256 x4": [256] * 4,
+               "uniform 512 x4": [512] * 4, "uniform 256 x16": [256] * 16,
+               "uniform 256 x64": [256] * 64, "uniform 512 x32": [512] * 32,
+               "uniform 1024 x16": [1024] * 16, "uniform 2048 x8": [2048] * 8,
+               "uniform 2048 x32": [2048] * 32, "uneven x64": W.uneven_lmax(),
+               "uneven x16": W.uneven_lmax()[:16]}
+    bat = []
+    for name, lm in batches.items():
+        plans = [Plan(L, W.healpix_geometry(L // 2), device=dev) for L in lm]
+        alms = [torch.from_numpy(W.random_alm(L, [10, i])).to(dev) for i, L in enumerate(lm)]
+        b = Batch(plans)
+        outs = b.new_maps()
+        default = b.config
+        ms = {}
+        for ch in (1, 2, 4):
+            for wv in (4, 8, 16, 32):
+                b.set_config(ch, wv)
+                ms[f"{ch},{wv}"] = _time_calls(lambda: b.alm2map(alms, outs), torch)
+        tiles = sum(((p.npairs + 127) // 128) * ((p.nm + 1) // 2) for p in plans)
+        bat.append({"batch": name, "maps": len(lm), "tiles_per_cu_at_128_pairs": tiles / ncu,
+                    "ms": ms, "fastest": min(ms, key=ms.get), "default": list(default)})
+        del b, plans, alms, outs
+        torch.cuda.empty_cache()
+    print(json.dumps({"shape_sweep": {"device_cus": ncu, "fp64_forward": fwd, "batch": bat}}),
+          flush=True)
+
+
 def run_grad(args, torch, np, W, dev):
     """The differentiation workload: 8 maps, l_max 1024, nside 512, loss
     0.5 ||alm2map(a) - d||^2 with d ~ N(0, 1) per pixel; one step = forward
@@ -284,6 +353,9 @@ def main() -> int:
                          "{256..2048}, one persistent launch, autotuned, graph replay)")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the l_max 64 / nside 32 single-map timing")
+    ap.add_argument("--shape-sweep", action="store_true",
+                    help="only time the launch shapes of the FP64 forward kernel and of the "
+                         "batch over sizes (the source of the default tables) and exit")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, copy this many MiB device to device (a copy of known "
                          "size for scaling hardware byte counters)")
@@ -306,6 +378,9 @@ def main() -> int:
     hip = _hip()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.shape_sweep:
+        shape_sweep(torch, np, W, dev)
+        return 0
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device=dev)
@@ -424,9 +499,7 @@ def main() -> int:
             "mixed_forms": forms,
             "fourier_stage": {"bytes_per_launch": fft_bytes_mixed * B,
                               "bytes_note": "complex64 Delta read once + float64 map written "
-                                            "once; the stage also transposes Delta to "
-                                            "ring-contiguous order (its traffic is not "
-                                            "counted as algorithmic)",
+                                            "once",
                               "achieved_GBps": fft_bytes_mixed * B /
                               (fb["stages_ms"]["ring_synthesis"] * 1e-3) / 1e9,
                               "frac_hbm": fft_bytes_mixed * B /

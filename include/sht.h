@@ -294,11 +294,15 @@ sht_status sht_alm2map_batch(sht_batch_t batch, const double *const *alms,
                              double *const *maps, void *ws, size_t ws_bytes, void *stream);
 
 /* Launch shape of the batch: chains (ring pairs per lane: 1, 2 or 4) and
- * persistent waves per compute unit (1..32). */
+ * persistent waves per compute unit (1..32).  The default comes from a table
+ * measured over sizes (Sec. 6.1: the best shape depends on the size), keyed
+ * by work tiles of 128 ring pairs per compute unit; every shape gives the
+ * same results. */
 sht_status sht_batch_get_config(sht_batch_t batch, int32_t *chains, int32_t *waves_per_cu);
 sht_status sht_batch_set_config(sht_batch_t batch, int32_t chains, int32_t waves_per_cu);
 
-/* Autotuner: times every (chains, waves per CU) candidate on the given
+/* Autotuner: times every (chains in {1, 2, 4}, waves per CU in {4, 8, 16, 32})
+ * candidate on the given
  * buffers (synchronising `stream`) and keeps the fastest.  If cache_path is
  * not NULL, a line "<batch signature> <chains> <waves_per_cu> <ms>" is looked
  * up first (no timing if found) and appended after tuning.  The outputs are

@@ -23,7 +23,27 @@ namespace {
 
 constexpr uint64_t kBatchMagic = 0x53485442'41544348ull;  // "SHTBATCH"
 const int kChainChoices[] = {1, 2, 4};
-const int kWaveChoices[] = {4, 8, 16};  // persistent waves per CU
+const int kWaveChoices[] = {4, 8, 16, 32};  // persistent waves per CU
+
+// Default launch shape of the batch by size (the best shape depends on the
+// input size, Sec. 6.1; Sec. 5 proposes tuning per size).  Key: work tiles of
+// 128 ring pairs (two chains per lane) per compute unit.  Measured on MI355X
+// (256 compute units) over batches of uniform l_max 128..2048 (4 to 64 maps)
+// and the uneven 16- and 64-map draws, every shape of {1, 2, 4} chains x
+// {4, 8, 16, 32} waves per CU: up to 4 tiles per CU two chains and 4 waves
+// are fastest, up to 16 four chains and 8 waves, above that four chains and
+// 16 waves (the residency limit of the four-chain kernel's 128 VGPRs; two
+// chains at 32 waves come within 1% at the largest sizes).  The former fixed
+// choice (2, 8) was up to 2.4x slower above 100 tiles per CU.
+struct BatchShapeRule {
+    double max_tiles_per_cu;
+    int chains, waves_per_cu;
+};
+constexpr BatchShapeRule kBatchShapeTable[] = {
+    {4.0, 2, 4},
+    {16.0, 4, 8},
+    {1e300, 4, 16},
+};
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -204,8 +224,15 @@ sht_status sht_plan_batch(sht_batch_t *out, const sht_plan_t *plans, int32_t n)
         delete b;
         return st;
     }
-    b->chains = 2;
-    b->waves_per_cu = 8;
+    {
+        const double tiles = (double)b->ntiles[chain_index(2)] / (double)std::max(1, b->num_cus);
+        for (const BatchShapeRule &r : kBatchShapeTable)
+            if (tiles <= r.max_tiles_per_cu) {
+                b->chains = r.chains;
+                b->waves_per_cu = r.waves_per_cu;
+                break;
+            }
+    }
     b->magic = kBatchMagic;
     *out = b;
     return SHT_OK;

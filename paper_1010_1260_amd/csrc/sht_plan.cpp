@@ -65,7 +65,7 @@ struct PairKeyHash {
 // have with one ring pair per lane, per compute unit.  More pairs per lane
 // give each wave independent recurrences to interleave but fewer waves to
 // hide latency with.  Measured on MI355X (256 compute units) over
-// l_max = 64..4096, nside = l_max / 2, 1..16 maps, with tune_fp64_chains.py:
+// l_max = 64..4096, nside = l_max / 2, 1..16 maps (bench.py --shape-sweep):
 // one pair per lane is fastest up to 8 waves per CU (up to 14% ahead), two
 // from 32 on (up to 33% ahead at l_max 4096), four never; the switch sits
 // between the two measured points.

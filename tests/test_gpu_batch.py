@@ -54,7 +54,7 @@ def test_batch_equals_single_plans_every_config(P):
     plans, alms, singles = _setup(P, lmaxes, 601)
     b = P.Batch(plans)
     for ch in (1, 2, 4):
-        for w in (1, 4, 16):
+        for w in (1, 4, 8, 16, 32):   # every entry of the default table among them
             b.set_config(ch, w)
             outs = b.alm2map(alms)
             torch.cuda.synchronize()
@@ -67,6 +67,23 @@ def test_batch_equals_single_plans_every_config(P):
         exp = ref.alm2map(L, g, alms[i].cpu().numpy())
         got = singles[i].cpu().numpy()
         assert np.linalg.norm(got - exp) <= 1e-12 * np.linalg.norm(exp)
+
+
+def test_batch_default_shape_follows_size(P):
+    """The default launch shape comes from the size table: (2 chains, 4 waves
+    per CU) up to 4 tiles of 128 ring pairs per CU, (4, 8) up to 16, (4, 16)
+    above."""
+    _say("batch default shape by size")
+    ncu = torch.cuda.get_device_properties(_dev()).multi_processor_count
+
+    def tiles_per_cu(plans):
+        return sum(((p.npairs + 127) // 128) * ((p.nm + 1) // 2) for p in plans) / ncu
+
+    for lmax, nmaps in [(16, 1), (256, 8), (512, 32)]:
+        plans = [P.Plan(lmax, W.healpix_geometry(lmax // 2)) for _ in range(nmaps)]
+        t = tiles_per_cu(plans)
+        exp = (2, 4) if t <= 4 else ((4, 8) if t <= 16 else (4, 16))
+        assert P.Batch(plans).config == exp, (lmax, nmaps, t)
 
 
 def test_batch_autotune_and_cache(P, tmp_path):
