@@ -232,6 +232,9 @@ sht_status sht_plan_batch(sht_batch_t *out, const sht_plan_t *plans, int32_t n)
                 b->waves_per_cu = r.waves_per_cu;
                 break;
             }
+        sht::log_line("batch maps=%d tiles of 128 pairs per CU=%.1f: launch shape %d chain(s) "
+                      "x %d waves per CU (size table); workspace %zu bytes",
+                      n, tiles, b->chains, b->waves_per_cu, b->ws_bytes);
     }
     b->magic = kBatchMagic;
     *out = b;
@@ -333,6 +336,9 @@ sht_status sht_batch_autotune(sht_batch_t b, const double *const *alms, double *
     (void)hipEventDestroy(e1);
     b->chains = best_ch;
     b->waves_per_cu = best_w;
+    if (s == SHT_OK)
+        sht::log_line("autotune batch: %d chain(s) x %d waves per CU, %.3f ms per call",
+                      best_ch, best_w, best / 3);
     if (s != SHT_OK) return s;
     if (cache_path && cache_path[0]) {
         std::ofstream outf(cache_path, std::ios::app);

@@ -266,6 +266,12 @@ hipError_t launch_batch_legendre(const BatchMap *maps, int nmaps, long long max_
                                  hipStream_t st);
 hipError_t launch_ring_synth_batch(const BatchClass *cls, const BatchMap *maps,
                                    double *const *outs, const void *ws, hipStream_t st);
+// Decision log: with SHT_LOG set in the environment (to anything but "0"),
+// plan and batch creation and the autotuners write one line per decision to
+// stderr (ring classes, radix lists, workspace sizes, launch shapes).
+bool log_enabled();
+void log_line(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
+
 // The forward transform of a plan into a caller workspace of at least
 // forward_workspace(p) bytes (no checks: the entry points validate).
 size_t forward_workspace(const sht_plan_s *p);

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdarg>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -279,6 +280,9 @@ const char *sht_status_string(sht_status s)
     }
     return "unknown sht_status";
 }
+
+static size_t fwd_workspace_bytes(const sht_plan_s *p);
+static size_t workspace_bytes(const sht_plan_s *p);
 
 sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
 {
@@ -598,6 +602,39 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
                                  256);
     p->fwd_chains = default_fwd_chains(p);
     p->magic = sht::kPlanMagic;
+    if (sht::log_enabled()) {
+        static const char *kPrec[] = {"fp64", "fp32_mfma", "bf16x3_mfma", "f16x2_mfma"};
+        int nblue = 0, nfast = 0;
+        for (int r = 0; r < R; ++r) {
+            nblue += rings[r].nb != 0;
+            nfast += rings[r].np > 0;
+        }
+        sht::log_line("plan l_max=%d nm=%d m_max=%d rings=%d pairs=%d maps=%d precision=%s "
+                      "delta=%s", p->lmax, p->nm, p->mmax, R, p->npairs, p->nmaps,
+                      kPrec[p->precision], delta_f32(p) ? "complex64" : "complex128");
+        sht::log_line("plan synthesis rings: fast path %d (Stockham in registers), size classes "
+                      "%d / %d / %d (256 / 512 / 1024 threads), of which Bluestein %d",
+                      nfast, p->scls[0].count, p->scls[1].count, p->scls[2].count, nblue);
+        // the radix lists of the three longest fast-path ring lengths
+        std::map<int, int> longest;   // nphi -> a ring of that length
+        for (int r = 0; r < R; ++r)
+            if (rings[r].np > 0) longest[-rings[r].n] = r;
+        int shown = 0;
+        for (const auto &kv : longest) {
+            if (shown++ == 3) break;
+            const sht::RingDesc &g = rings[kv.second];
+            char rl[64];
+            int o = 0;
+            for (int q = 0; q < g.np; ++q)
+                o += std::snprintf(rl + o, sizeof rl - o, q ? "x%d" : "%d",
+                                   (int)((g.rads >> (5 * q)) & 31));
+            sht::log_line("plan fast ring nphi=%d: half length %d = %s", g.n, g.clen, rl);
+        }
+        sht::log_line("plan workspace forward=%zu full=%zu bytes, device tables=%zu bytes; "
+                      "FP64 forward launch shape %d pair(s) per lane (size table)",
+                      fwd_workspace_bytes(p), workspace_bytes(p), p->table_bytes,
+                      p->fwd_chains);
+    }
     *out = p;
     return SHT_OK;
 }
@@ -684,6 +721,26 @@ sht_status sht_delta2map(sht_plan_t p, const double *delta, double *map, void *s
 }  // extern "C"
 
 namespace sht {
+
+bool log_enabled()
+{
+    static const bool on = [] {
+        const char *v = std::getenv("SHT_LOG");
+        return v && v[0] && std::strcmp(v, "0") != 0;
+    }();
+    return on;
+}
+
+void log_line(const char *fmt, ...)
+{
+    if (!log_enabled()) return;
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "sht: %s\n", buf);
+}
 
 size_t forward_workspace(const sht_plan_s *p) { return fwd_workspace_bytes(p); }
 
@@ -785,6 +842,8 @@ sht_status sht_plan_autotune(sht_plan_t p, const double *alm, double *map, void 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     p->fwd_chains = (s == SHT_OK) ? best_ch : start;
+    if (s == SHT_OK)
+        sht::log_line("autotune plan: %d pair(s) per lane, %.3f ms per call", best_ch, best / 3);
     if (s != SHT_OK) return s;
     if (cache_path && cache_path[0]) {
         std::ofstream outf(cache_path, std::ios::app);

@@ -153,3 +153,33 @@ def test_forward_workspace_suffices_for_synthesis(P):
     got = out.cpu().numpy()
     for i in range(nmaps):
         assert _rel(got[i], ref.alm2map(lmax, g, alms[i])) < 1e-12
+
+
+def test_decision_log(P, tmp_path):
+    """SHT_LOG=1 makes plan and batch creation and the autotuner report their
+    decisions on stderr; without it the library prints nothing."""
+    import subprocess
+    import sys as _sys
+    _say("decision log")
+    root = __import__("os").path.dirname(__import__("os").path.dirname(__import__("os").path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import torch, workloads as W\n"
+        "from paper_1010_1260_amd import Plan, Batch\n"
+        "p = Plan(128, W.healpix_geometry(64))\n"
+        "a = torch.from_numpy(W.random_alm(128, [7])).to('cuda:0').reshape(1, -1)\n"
+        "p.autotune(a)\n"
+        "b = Batch([p, Plan(64, W.healpix_geometry(32))])\n"
+        "torch.cuda.synchronize()\n" % root)
+    env = dict(__import__("os").environ, SHT_LOG="1")
+    r = subprocess.run([_sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr
+    for key in ("sht: plan l_max=128", "sht: plan synthesis rings: fast path",
+                "sht: plan fast ring nphi=256: half length 128 = 16x8",
+                "sht: autotune plan:", "sht: batch maps=2"):
+        assert key in r.stderr, (key, r.stderr)
+    env["SHT_LOG"] = "0"
+    r = subprocess.run([_sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                       timeout=120)
+    assert r.returncode == 0 and "sht:" not in r.stderr
