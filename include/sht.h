@@ -29,8 +29,11 @@
  *    alm + 2 * b * nalm (doubles), its pixels at map + b * npix.
  *
  * Ownership and streams
- *  - The plan owns only its own device tables, allocated on the device that
- *    is current when sht_plan is called.  Every device pointer passed to the
+ *  - The plan owns its own device tables, allocated on the device that is
+ *    current when sht_plan is called, and one auxiliary stream with two
+ *    events: for large plans the synthesis forks part of its Fourier work
+ *    onto that stream and joins it back into `stream` before returning, so
+ *    every call stays ordered on `stream`.  Every device pointer passed to the
  *    other calls (coefficients, maps, workspace) is owned by the caller and
  *    must be on that device, 16-byte aligned.
  *  - sht_alm2map* and sht_alm2map_adjoint* only enqueue kernels on `stream`
@@ -38,7 +41,10 @@
  *    and never synchronise, so they can be captured into a HIP graph.
  *  - A plan is immutable after creation, apart from its launch shape
  *    (sht_plan_set_config, sht_plan_autotune), which changes no result.
- *    Calls on different streams are safe if they use distinct workspaces.
+ *    Calls on different streams are safe if they use distinct workspaces
+ *    (host threads take turns through the fork and join).  While a call is
+ *    being captured into a HIP graph, the plan's auxiliary stream is part of
+ *    the capture: do not use the same plan from another thread meanwhile.
  *
  * Errors: every call returns an sht_status; nothing throws across the ABI.
  * Argument errors are detected on the host before anything is enqueued.

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "sht.h"
@@ -217,6 +218,11 @@ struct sht_plan_s {
     int fwd_chains;      // ring pairs per lane of the FP64 forward Legendre kernel (1, 2, 4)
     int num_cus;         // compute units of the plan's device
     size_t ws_ap_bytes;  // workspace: prescaled coefficients
+    // the fast-path synthesis of large plans runs on aux_stream beside the
+    // size-class kernels on the caller's stream (fork / join by the events)
+    hipStream_t aux_stream;
+    hipEvent_t ev_fork, ev_join;
+    std::mutex fork_mu;    // one fork / launches / join sequence at a time
     size_t ws_delta_bytes;   // workspace: forward Delta (complex64 for the mixed forms)
     size_t ws_dt_bytes;      // workspace: adjoint Delta~ (complex128)
 };
