@@ -199,6 +199,10 @@ sht_status sht_plan_batch(sht_batch_t *out, const sht_plan_t *plans, int32_t n)
             const sht_plan_s *p = plans[i];
             for (int r = 0; r < p->nrings; ++r)
                 if (p->ring_sclass[r] == c) {
+                    if (c == sht::kBlueClass) {   // the batch takes FP64 plans only
+                        st = SHT_ERR_UNSUPPORTED;
+                        break;
+                    }
                     items.push_back(make_int2(i, r));
                     if (c == sht::kFastClass)
                         sht::fast_lds_add(lds, p->ring_n[r], p->mmax);

@@ -1,4 +1,5 @@
-// Per-ring Fourier step of alm2map and of its adjoint, FP64, for gfx950.
+// Per-ring Fourier step of alm2map and of its adjoint for gfx950: FP64,
+// except the synthesis fast paths of the mixed forms (complex64 passes).
 //
 // Synthesis (Eq. Delta2map, Sec. 2.1, and the wrap rule of Sec. 2.2.2):
 //     s_j = sum_{m=-mmax}^{mmax} Delta_m e^{i m (phi0 + 2 pi j / n)},  Delta_{-m} = conj(Delta_m).
@@ -21,8 +22,13 @@
 // next ring's while the current one is transformed), folds them through a
 // padded LDS buffer and runs Stockham passes of radix 16, 8, 4, 2, 7, 5, 3
 // with the butterflies held in registers, the half-length pre-processing
-// fused into the first pass and the pixels stored from the last.  The other
-// rings are grouped by FFT length into three size classes (up to 2048, 4096
+// fused into the first pass and the pixels stored from the last.  Its passes
+// run in complex128 for FP64 plans and in complex64 for the mixed forms,
+// whose Delta is complex64 (the fold adds in FP64 either way).  The mixed
+// forms also take even rings whose half length is twice a non-7-smooth
+// number on a Bluestein fast path: a persistent 512-thread kernel that runs
+// the even- and odd-indexed Bluestein convolutions side by side in two
+// complex64 buffers.  The other rings are grouped by FFT length into three size classes (up to 2048, 4096
 // and 8192 points) run by 256-, 512- and 1024-thread workgroups, each with an
 // LDS layout computed on the host for the class.  There, DFTs of 7-smooth length run as
 // a Stockham auto-sort FFT (radices 8, 4, 2, 3, 5 and 7; every pass loads its
@@ -60,6 +66,32 @@ __device__ inline double2 muli(double2 a, int sign)
     return sign > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
 }
 
+// The same operations on complex64, for the FP32 Fourier passes of the mixed
+// forms' fast path.
+__device__ inline float2 cmul(float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ inline float2 conjd(float2 a) { return make_float2(a.x, -a.y); }
+__device__ inline float2 muli(float2 a, int sign)
+{
+    return sign > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// Complex element type C from real parts, and conversions between the two
+// precisions (rounded once).
+template <typename C> __device__ inline C cplx(double x, double y);
+template <> __device__ inline double2 cplx<double2>(double x, double y) { return make_double2(x, y); }
+template <> __device__ inline float2 cplx<float2>(double x, double y)
+{
+    return make_float2((float)x, (float)y);
+}
+template <typename C> __device__ inline C cvt(double2 v) { return cplx<C>(v.x, v.y); }
+__device__ inline double2 todbl(double2 v) { return v; }
+__device__ inline double2 todbl(float2 v) { return make_double2((double)v.x, (double)v.y); }
+
 // cos / sin of 2 pi q / R (correctly rounded)
 template <int R> struct Roots;
 template <> struct Roots<3> {
@@ -82,62 +114,66 @@ template <> struct Roots<7> {
 };
 
 // y_k = sum_r v_r e^{sign 2 pi i r k / R}
-template <int R>
-__device__ inline void small_dft(double2 (&v)[R], int sign)
+__device__ inline double fmaS(double a, double b, double c) { return fma(a, b, c); }
+__device__ inline float fmaS(float a, float b, float c) { return fmaf(a, b, c); }
+
+template <int R, typename C>
+__device__ inline void small_dft(C (&v)[R], int sign)
 {
+    typedef decltype(C::x) S;
     if constexpr (R == 2) {
-        const double2 a = v[0], b = v[1];
+        const C a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
     } else if constexpr (R == 4) {
-        const double2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
-        const double2 s13 = cadd(v[1], v[3]), d13 = muli(csub(v[1], v[3]), sign);
+        const C s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+        const C s13 = cadd(v[1], v[3]), d13 = muli(csub(v[1], v[3]), sign);
         v[0] = cadd(s02, s13);
         v[2] = csub(s02, s13);
         v[1] = cadd(d02, d13);
         v[3] = csub(d02, d13);
     } else if constexpr (R == 16) {
         // 16 = 4 x 4: r = 4a + b, k = c + 4d, w^(rk) = w4^(ac) w16^(bc) w4^(bd)
-        double2 u[4][4];   // u[b][c]
+        C u[4][4];   // u[b][c]
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            double2 t[4] = {v[b], v[4 + b], v[8 + b], v[12 + b]};
-            small_dft<4>(t, sign);
+            C t[4] = {v[b], v[4 + b], v[8 + b], v[12 + b]};
+            small_dft<4, C>(t, sign);
 #pragma unroll
             for (int c = 0; c < 4; ++c) u[b][c] = t[c];
         }
-        constexpr double c1 = 0x1.d906bcf328d46p-1;  // cos(pi/8), correctly rounded
-        constexpr double s1 = 0x1.87de2a6aea963p-2;  // sin(pi/8)
-        constexpr double hh = 0x1.6a09e667f3bcdp-1;  // 1/sqrt(2)
+        constexpr S c1 = (S) 0x1.d906bcf328d46p-1;  // cos(pi/8), correctly rounded
+        constexpr S s1 = (S) 0x1.87de2a6aea963p-2;  // sin(pi/8)
+        constexpr S hh = (S) 0x1.6a09e667f3bcdp-1;  // 1/sqrt(2)
         // w16^e = (cos, sign sin) of 2 pi e / 16 for e = b c, b, c in 1..3
-        const double sg = (double)sign;
-        u[1][1] = cmul(u[1][1], make_double2(c1, sg * s1));
-        u[1][2] = cmul(u[1][2], make_double2(hh, sg * hh));
-        u[1][3] = cmul(u[1][3], make_double2(s1, sg * c1));
-        u[2][1] = cmul(u[2][1], make_double2(hh, sg * hh));
+        const S sg = (S)sign;
+        u[1][1] = cmul(u[1][1], cplx<C>(c1, sg * s1));
+        u[1][2] = cmul(u[1][2], cplx<C>(hh, sg * hh));
+        u[1][3] = cmul(u[1][3], cplx<C>(s1, sg * c1));
+        u[2][1] = cmul(u[2][1], cplx<C>(hh, sg * hh));
         u[2][2] = muli(u[2][2], sign);
-        u[2][3] = cmul(u[2][3], make_double2(-hh, sg * hh));
-        u[3][1] = cmul(u[3][1], make_double2(s1, sg * c1));
-        u[3][2] = cmul(u[3][2], make_double2(-hh, sg * hh));
-        u[3][3] = cmul(u[3][3], make_double2(-c1, -sg * s1));
+        u[2][3] = cmul(u[2][3], cplx<C>(-hh, sg * hh));
+        u[3][1] = cmul(u[3][1], cplx<C>(s1, sg * c1));
+        u[3][2] = cmul(u[3][2], cplx<C>(-hh, sg * hh));
+        u[3][3] = cmul(u[3][3], cplx<C>(-c1, -sg * s1));
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            double2 t[4] = {u[0][c], u[1][c], u[2][c], u[3][c]};
-            small_dft<4>(t, sign);
+            C t[4] = {u[0][c], u[1][c], u[2][c], u[3][c]};
+            small_dft<4, C>(t, sign);
 #pragma unroll
             for (int d = 0; d < 4; ++d) v[c + 4 * d] = t[d];
         }
     } else if constexpr (R == 8) {
         // two radix-4 DFTs of the even and odd inputs, combined with w8^k
-        double2 e[4] = {v[0], v[2], v[4], v[6]};
-        double2 o[4] = {v[1], v[3], v[5], v[7]};
-        small_dft<4>(e, sign);
-        small_dft<4>(o, sign);
-        constexpr double h = 0x1.6a09e667f3bcdp-1;  // 1/sqrt(2), correctly rounded
+        C e[4] = {v[0], v[2], v[4], v[6]};
+        C o[4] = {v[1], v[3], v[5], v[7]};
+        small_dft<4, C>(e, sign);
+        small_dft<4, C>(o, sign);
+        constexpr S h = (S)0x1.6a09e667f3bcdp-1;  // 1/sqrt(2), correctly rounded
         // w8 = e^{sign i pi/4}: w8^1 o1, w8^2 o2 = sign i o2, w8^3 o3
-        const double2 t1 = make_double2(h * (o[1].x - sign * o[1].y), h * (o[1].y + sign * o[1].x));
-        const double2 t2 = muli(o[2], sign);
-        const double2 t3 = make_double2(-h * (o[3].x + sign * o[3].y), h * (sign * o[3].x - o[3].y));
+        const C t1 = cplx<C>(h * (o[1].x - sign * o[1].y), h * (o[1].y + sign * o[1].x));
+        const C t2 = muli(o[2], sign);
+        const C t3 = cplx<C>(-h * (o[3].x + sign * o[3].y), h * (sign * o[3].x - o[3].y));
         v[0] = cadd(e[0], o[0]);
         v[4] = csub(e[0], o[0]);
         v[1] = cadd(e[1], t1);
@@ -148,31 +184,31 @@ __device__ inline void small_dft(double2 (&v)[R], int sign)
         v[7] = csub(e[3], t3);
     } else {
         // odd R: pair r with R - r
-        double2 sp[R / 2], dm[R / 2];
+        C sp[R / 2], dm[R / 2];
 #pragma unroll
         for (int r = 1; r <= R / 2; ++r) {
             sp[r - 1] = cadd(v[r], v[R - r]);
             dm[r - 1] = csub(v[r], v[R - r]);
         }
-        double2 y[R];
-        double2 y0 = v[0];
+        C y[R];
+        C y0 = v[0];
 #pragma unroll
         for (int r = 0; r < R / 2; ++r) y0 = cadd(y0, sp[r]);
         y[0] = y0;
 #pragma unroll
         for (int k = 1; k < R; ++k) {
-            double ar = v[0].x, ai = v[0].y, br = 0.0, bi = 0.0;
+            S ar = v[0].x, ai = v[0].y, br = 0, bi = 0;
 #pragma unroll
             for (int r = 1; r <= R / 2; ++r) {
-                const double c = Roots<R>::c[(r * k) % R];
-                const double s = Roots<R>::s[(r * k) % R];
-                ar = fma(sp[r - 1].x, c, ar);
-                ai = fma(sp[r - 1].y, c, ai);
-                br = fma(dm[r - 1].x, s, br);
-                bi = fma(dm[r - 1].y, s, bi);
+                const S c = (S)Roots<R>::c[(r * k) % R];
+                const S s = (S)Roots<R>::s[(r * k) % R];
+                ar = fmaS(sp[r - 1].x, c, ar);
+                ai = fmaS(sp[r - 1].y, c, ai);
+                br = fmaS(dm[r - 1].x, s, br);
+                bi = fmaS(dm[r - 1].y, s, bi);
             }
             // + sign * i * (b)
-            y[k] = sign > 0 ? make_double2(ar - bi, ai + br) : make_double2(ar + bi, ai - br);
+            y[k] = sign > 0 ? cplx<C>(ar - bi, ai + br) : cplx<C>(ar + bi, ai - br);
         }
 #pragma unroll
         for (int k = 0; k < R; ++k) v[k] = y[k];
@@ -186,19 +222,19 @@ __device__ inline void small_dft(double2 (&v)[R], int sign)
 // never wait on global memory.
 constexpr int kTwEntries = 64 + 256;
 
-template <int NT>
-__device__ __attribute__((always_inline)) inline void load_tw(double2 *T,
-                                                              const double2 *__restrict__ tab,
+template <int NT, typename C>
+__device__ __attribute__((always_inline)) inline void load_tw(C *T, const double2 *__restrict__ tab,
                                                               int L)
 {
     const int n1 = (L + 63) >> 6;
     for (int e = threadIdx.x; e < 64 + n1; e += NT) {
         const int t = (e < 64) ? e : 64 * (e - 64);
-        T[e] = (t < L) ? tab[t] : make_double2(1.0, 0.0);
+        T[e] = (t < L) ? cvt<C>(tab[t]) : cplx<C>(1.0, 0.0);
     }
 }
 
-__device__ inline double2 tw_at(const double2 *T, int t)
+template <typename C>
+__device__ inline C tw_at(const C *T, int t)
 {
     return cmul(T[64 + (t >> 6)], T[t & 63]);
 }
@@ -695,8 +731,8 @@ __device__ __attribute__((always_inline)) inline void synth_ring(double2 *buf, c
 //
 // One pass of radix R over the h-point buffer (input index j + r h/R,
 // output index (j / Ns) Ns R + j % Ns + r Ns).  T: the ring's n-th roots.
-template <int R, int NT>
-__device__ __attribute__((always_inline)) inline void fast_pass(double2 *buf, const double2 *T,
+template <int R, int NT, typename C>
+__device__ __attribute__((always_inline)) inline void fast_pass(C *buf, const C *T,
                                                                 int h, int Ns, bool first,
                                                                 bool last, double *__restrict__ out)
 {
@@ -709,7 +745,7 @@ __device__ __attribute__((always_inline)) inline void fast_pass(double2 *buf, co
     // case would stay live across all of them
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    double2 v[MAXQ][R];
+    C v[MAXQ][R];
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
         const int j = tid + q * NT;
@@ -719,8 +755,8 @@ __device__ __attribute__((always_inline)) inline void fast_pass(double2 *buf, co
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int k = j + r * nb;
-                    const double2 Fk = buf[PadIdx::at(k)], Fk2 = buf[PadIdx::at(h - k)];
-                    const double2 e1 = cadd(Fk, conjd(Fk2)), o1 = csub(Fk, conjd(Fk2));
+                    const C Fk = buf[PadIdx::at(k)], Fk2 = buf[PadIdx::at(h - k)];
+                    const C e1 = cadd(Fk, conjd(Fk2)), o1 = csub(Fk, conjd(Fk2));
                     v[q][r] = cadd(e1, muli(cmul(tw_at(T, k), o1), +1));
                 }
             } else {
@@ -731,8 +767,8 @@ __device__ __attribute__((always_inline)) inline void fast_pass(double2 *buf, co
                 const int jq = (int)__umulhi((unsigned)j, magic);
                 const int ts = tstep0 * (j - jq * Ns);
                 if (ts != 0) {
-                    const double2 w1 = tw_at(T, ts);
-                    double2 wr = w1;
+                    const C w1 = tw_at(T, ts);
+                    C wr = w1;
 #pragma unroll
                     for (int r = 1; r < R; ++r) {
                         v[q][r] = cmul(v[q][r], wr);
@@ -740,13 +776,14 @@ __device__ __attribute__((always_inline)) inline void fast_pass(double2 *buf, co
                     }
                 }
             }
-            small_dft<R>(v[q], +1);
+            small_dft<R, C>(v[q], +1);
         }
     }
     if (last) {
         // Ns R = h: j < Ns, output z_{j + r nb} = pixels 2 (j + r nb), 2 (j + r nb) + 1
         const bool al = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
         double2 *o2 = reinterpret_cast<double2 *>(out);
+        // pixels are float64 whatever the precision of the passes
 #pragma unroll
         for (int q = 0; q < MAXQ; ++q) {
             const int j = tid + q * NT;
@@ -755,10 +792,10 @@ __device__ __attribute__((always_inline)) inline void fast_pass(double2 *buf, co
                 for (int r = 0; r < R; ++r) {
                     const int i = j + r * nb;
                     if (al) {
-                        o2[i] = v[q][r];
+                        o2[i] = todbl(v[q][r]);
                     } else {
-                        out[2 * i] = v[q][r].x;
-                        out[2 * i + 1] = v[q][r].y;
+                        out[2 * i] = (double)v[q][r].x;
+                        out[2 * i + 1] = (double)v[q][r].y;
                     }
                 }
             }
@@ -787,35 +824,36 @@ __device__ __attribute__((always_inline)) inline void fast_pass(double2 *buf, co
 // is read only by bin m, whose own thread then overwrites it with F_m.  Rings
 // with fewer bins than threads split each bin's aliases over G = NT / bins
 // threads and add the G partial sums in a fixed order.  Ends with a barrier.
-template <int NT>
+template <int NT, typename DT>
 struct FastModes {
-    double2 v[kFastMaxModes / NT];
+    static constexpr int Q = (kFastMaxModes + NT - 1) / NT;
+    DT v[Q];   // as stored (complex64 or complex128), widened at use
 };
 
 // Loads of the fold: modes m = tid + q NT of one ring (issued together).
 template <int NT, typename DT>
-__device__ __attribute__((always_inline)) inline void load_fast(FastModes<NT> &raw,
+__device__ __attribute__((always_inline)) inline void load_fast(FastModes<NT, DT> &raw,
                                                                 const DT *__restrict__ drow,
                                                                 long long dstride,
                                                                 const int *__restrict__ minv,
                                                                 int mcontig, int mmax)
 {
-    constexpr int QM = kFastMaxModes / NT;
+    constexpr int QM = FastModes<NT, DT>::Q;
     const int tid = threadIdx.x;
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
         const int m = tid + q * NT;
-        raw.v[q] = (m <= mmax) ? load_mode(drow, dstride, minv, mcontig, m)
-                               : make_double2(0.0, 0.0);
+        const int i = (m <= mmax) ? (mcontig ? m : minv[m]) : -1;
+        raw.v[q] = (i >= 0) ? drow[(long long)i * dstride] : DT{};
     }
 }
 
-template <int NT>
-__device__ __attribute__((always_inline)) inline void fold_fast(double2 *buf, const RingDesc &d,
-                                                                const FastModes<NT> &raw,
+template <int NT, typename C, typename DT>
+__device__ __attribute__((always_inline)) inline void fold_fast(C *buf, const RingDesc &d,
+                                                                const FastModes<NT, DT> &raw,
                                                                 int mmax)
 {
-    constexpr int QM = kFastMaxModes / NT;
+    constexpr int QM = FastModes<NT, DT>::Q;
     const int tid = threadIdx.x;
     double2 ph, step;   // e^{i tid phi0}, e^{i NT phi0}
     {
@@ -829,9 +867,9 @@ __device__ __attribute__((always_inline)) inline void fold_fast(double2 *buf, co
     for (int q = 0; q < QM; ++q) {
         const int m = tid + q * NT;
         if (m <= mmax) {
-            double2 v = raw.v[q];
+            double2 v = widen(raw.v[q]);
             if (m == 0) v.y = 0.0;
-            buf[PadIdx::at(m)] = cmul(ph, v);
+            buf[PadIdx::at(m)] = cvt<C>(cmul(ph, v));
         }
         ph = cmul(ph, step);
     }
@@ -842,9 +880,9 @@ __device__ __attribute__((always_inline)) inline void fold_fast(double2 *buf, co
     if (n > mmax) {
         // at most one direct mode (m = k) and one mirrored mode (m = n - k)
         for (int k = tid; k <= h; k += NT) {
-            double2 F = (k <= mmax) ? buf[PadIdx::at(k)] : make_double2(0.0, 0.0);
-            if (k >= 1 && n - k <= mmax) F = cadd(F, conjd(buf[PadIdx::at(n - k)]));
-            buf[PadIdx::at(k)] = F;
+            double2 F = (k <= mmax) ? todbl(buf[PadIdx::at(k)]) : make_double2(0.0, 0.0);
+            if (k >= 1 && n - k <= mmax) F = cadd(F, conjd(todbl(buf[PadIdx::at(n - k)])));
+            buf[PadIdx::at(k)] = cvt<C>(F);
         }
     } else if (B >= NT) {
         for (int k = tid; k <= h; k += NT) {
@@ -852,15 +890,15 @@ __device__ __attribute__((always_inline)) inline void fold_fast(double2 *buf, co
             double sr = 0.0, si = 0.0;
             for (int j = 0; j <= jmax; ++j) {
                 if (k + j * n <= mmax) {
-                    const double2 v = buf[PadIdx::at(k + j * n)];
+                    const double2 v = todbl(buf[PadIdx::at(k + j * n)]);
                     sr += v.x; si += v.y;
                 }
                 if (j >= 1) {
-                    const double2 v = buf[PadIdx::at(j * n - k)];
+                    const double2 v = todbl(buf[PadIdx::at(j * n - k)]);
                     sr += v.x; si -= v.y;
                 }
             }
-            buf[PadIdx::at(k)] = make_double2(sr, si);
+            buf[PadIdx::at(k)] = cplx<C>(sr, si);
         }
     } else {
         const int G = NT / B;
@@ -870,40 +908,40 @@ __device__ __attribute__((always_inline)) inline void fold_fast(double2 *buf, co
             const int jmax = (mmax + kk) / n;
             for (int j = g; j <= jmax; j += G) {
                 if (kk + j * n <= mmax) {
-                    const double2 v = buf[PadIdx::at(kk + j * n)];
+                    const double2 v = todbl(buf[PadIdx::at(kk + j * n)]);
                     sr += v.x; si += v.y;
                 }
                 if (j >= 1) {
-                    const double2 v = buf[PadIdx::at(j * n - kk)];
+                    const double2 v = todbl(buf[PadIdx::at(j * n - kk)]);
                     sr += v.x; si -= v.y;
                 }
             }
         }
         __syncthreads();
-        if (g < G) buf[PadIdx::at(g * B + kk)] = make_double2(sr, si);
+        if (g < G) buf[PadIdx::at(g * B + kk)] = cplx<C>(sr, si);
         __syncthreads();
         if (tid < B) {
             // column tid of the partials; entry 0 of it is this thread's own
             double tr = 0.0, ti = 0.0;
             for (int q = 0; q < G; ++q) {
-                const double2 v = buf[PadIdx::at(q * B + tid)];
+                const double2 v = todbl(buf[PadIdx::at(q * B + tid)]);
                 tr += v.x; ti += v.y;
             }
-            buf[PadIdx::at(tid)] = make_double2(tr, ti);
+            buf[PadIdx::at(tid)] = cplx<C>(tr, ti);
         }
     }
     __syncthreads();
 }
 
-template <int NT>
-__device__ __attribute__((always_inline)) inline void fft_fast(double2 *buf, const double2 *T,
+template <int NT, typename C>
+__device__ __attribute__((always_inline)) inline void fft_fast(C *buf, const C *T,
                                                                const RingDesc &d,
                                                                double *__restrict__ out);
 
 // Synthesis of one fast-path ring: buf = padded spectrum buffer, T = LDS
 // twiddle table, out = the ring's first pixel.
-template <int NT, typename DT>
-__device__ __attribute__((always_inline)) inline void synth_fast(double2 *buf, double2 *T,
+template <int NT, typename C, typename DT>
+__device__ __attribute__((always_inline)) inline void synth_fast(C *buf, C *T,
                                                                  const RingDesc &d,
                                                                  const double2 *__restrict__ pool,
                                                                  const DT *__restrict__ drow,
@@ -913,16 +951,16 @@ __device__ __attribute__((always_inline)) inline void synth_fast(double2 *buf, d
                                                                  double *__restrict__ out)
 {
     load_tw<NT>(T, pool + d.tw, d.n);
-    FastModes<NT> raw;
+    FastModes<NT, DT> raw;
     load_fast<NT>(raw, drow, dstride, minv, mcontig, mmax);
     fold_fast<NT>(buf, d, raw, mmax);
-    fft_fast<NT>(buf, T, d, out);
+    fft_fast<NT, C>(buf, T, d, out);
 }
 
 // The Stockham passes of a fast-path ring (after the fold) and the pixel
 // stores of the last one.
-template <int NT>
-__device__ __attribute__((always_inline)) inline void fft_fast(double2 *buf, const double2 *T,
+template <int NT, typename C>
+__device__ __attribute__((always_inline)) inline void fft_fast(C *buf, const C *T,
                                                                const RingDesc &d,
                                                                double *__restrict__ out)
 {
@@ -932,13 +970,13 @@ __device__ __attribute__((always_inline)) inline void fft_fast(double2 *buf, con
         const int R = (int)((d.rads >> (5 * p)) & 31);
         const bool first = p == 0, last = p == d.np - 1;
         switch (R) {
-        case 16: fast_pass<16, NT>(buf, T, h, Ns, first, last, out); break;
-        case 8: fast_pass<8, NT>(buf, T, h, Ns, first, last, out); break;
-        case 4: fast_pass<4, NT>(buf, T, h, Ns, first, last, out); break;
-        case 2: fast_pass<2, NT>(buf, T, h, Ns, first, last, out); break;
-        case 7: fast_pass<7, NT>(buf, T, h, Ns, first, last, out); break;
-        case 5: fast_pass<5, NT>(buf, T, h, Ns, first, last, out); break;
-        default: fast_pass<3, NT>(buf, T, h, Ns, first, last, out); break;
+        case 16: fast_pass<16, NT, C>(buf, T, h, Ns, first, last, out); break;
+        case 8: fast_pass<8, NT, C>(buf, T, h, Ns, first, last, out); break;
+        case 4: fast_pass<4, NT, C>(buf, T, h, Ns, first, last, out); break;
+        case 2: fast_pass<2, NT, C>(buf, T, h, Ns, first, last, out); break;
+        case 7: fast_pass<7, NT, C>(buf, T, h, Ns, first, last, out); break;
+        case 5: fast_pass<5, NT, C>(buf, T, h, Ns, first, last, out); break;
+        default: fast_pass<3, NT, C>(buf, T, h, Ns, first, last, out); break;
         }
         Ns *= R;
     }
@@ -951,15 +989,31 @@ __device__ __attribute__((always_inline)) inline void fft_fast(double2 *buf, con
 // XCD take its items in turn.  The loads of a workgroup's
 // next ring are issued before the Fourier passes of the current one, so that
 // their latency is hidden behind the passes.
+// The Fourier passes run in the precision of Delta: complex128 for FP64
+// plans, complex64 for the mixed forms (whose Delta carries FP32 sums; the
+// fold still adds the aliases in FP64).  The complex64 buffer is half the LDS,
+// so four workgroups share a CU instead of two.
+template <typename DT> struct FastPrec;
+template <> struct FastPrec<double2> {
+    typedef double2 C;
+    static constexpr int kBlocks = 2;
+};
+template <> struct FastPrec<float2> {
+    typedef float2 C;
+    static constexpr int kBlocks = 3;
+};
+
 template <typename DT>
-__global__ __launch_bounds__(kFastThreads, 2) void k_ring_synth_fast(
+__global__ __launch_bounds__(kFastThreads, FastPrec<DT>::kBlocks) void k_ring_synth_fast(
     const int *__restrict__ ids, int count, int nmaps, const RingDesc *__restrict__ rings,
     const double2 *__restrict__ pool, const DT *__restrict__ delta,
     const int *__restrict__ minv, int mcontig, int mmax, int nm, int nrings,
     double *__restrict__ map, long long npix, RingLds lds)
 {
-    extern __shared__ double2 buf[];
-    double2 *T = buf + lds.fft_entries;
+    typedef typename FastPrec<DT>::C C;
+    extern __shared__ double2 lds_raw[];
+    C *buf = reinterpret_cast<C *>(lds_raw);
+    C *T = buf + lds.fft_entries;
     const long long total = (long long)count * nmaps;
     const int per = (int)(gridDim.x / 8);
     const int x = (int)(blockIdx.x % 8), w = (int)(blockIdx.x / 8);
@@ -970,7 +1024,7 @@ __global__ __launch_bounds__(kFastThreads, 2) void k_ring_synth_fast(
     ring_item(it, count, i, bi);
     long long b = bi;
     int r = ids[i];
-    FastModes<kFastThreads> raw;
+    FastModes<kFastThreads, DT> raw;
     load_fast<kFastThreads>(raw, delta + b * nm * nrings + r, nrings, minv, mcontig, mmax);
     for (bool first = true;; first = false) {
         const RingDesc d = rings[r];
@@ -985,7 +1039,7 @@ __global__ __launch_bounds__(kFastThreads, 2) void k_ring_synth_fast(
             r = ids[i];
             load_fast<kFastThreads>(raw, delta + b * nm * nrings + r, nrings, minv, mcontig, mmax);
         }
-        fft_fast<kFastThreads>(buf, T, d, out);
+        fft_fast<kFastThreads, C>(buf, T, d, out);
         if (nx >= hi) break;
         it = nx;
     }
@@ -1000,8 +1054,257 @@ __global__ __launch_bounds__(kFastThreads, 2) void k_ring_synth_batch_fast(
     const BatchMap &bm = maps[it.x];
     const RingDesc d = bm.rings[it.y];
     const double2 *delta = reinterpret_cast<const double2 *>(ws + bm.delta_off);
-    synth_fast<kFastThreads>(buf, buf + lds.fft_entries, d, bm.pool, delta + it.y, bm.nrings,
-                             bm.minv, bm.mcontig, bm.mmax, outs[it.x] + d.start);
+    synth_fast<kFastThreads, double2>(buf, buf + lds.fft_entries, d, bm.pool, delta + it.y,
+                                      bm.nrings, bm.minv, bm.mcontig, bm.mmax,
+                                      outs[it.x] + d.start);
+}
+
+// ---------------------------------------------------------------------------
+// Bluestein fast path of the mixed forms: even rings whose half length
+// h = 2 len has a len that is not 7-smooth.  As in split_bluestein, the
+// h-point DFT of Z is z_j = E_j + w^j O_j, z_{j+len} = E_j - w^j O_j
+// (w = e^{2 pi i / h}), with E, O the len-point DFTs of Z's even- and
+// odd-indexed entries, each a Bluestein transform: a cyclic convolution of
+// 7-smooth length nb >= 2 len - 1 with the conjugate chirp.  The two
+// convolutions run side by side in two padded complex64 LDS buffers X and Y:
+// each Stockham pass takes its butterflies in both, so one barrier pair
+// serves the two.  The first forward pass forms Z from the folded spectrum
+// and multiplies by the chirp, the first inverse pass multiplies by the
+// kernel's spectrum bq, and the last inverse pass multiplies by the chirp,
+// combines E and O and writes the pixels.  The chirp
+// c_k = e^{i pi k^2 / len} = e^{2 pi i (k^2 mod h) / h} is read from the
+// ring's n-th roots (n = 2 h) in LDS.
+enum BlueIn { kBlueInZ, kBlueInBuf, kBlueInBq };
+
+struct BlueRing {
+    int h, len;
+    const double2 *bq;   // kernel spectrum DFT^-(conj chirp, wrapped) / nb
+    double *out;         // the ring's first pixel
+};
+
+// One pass of radix R over both nb-point buffers (input index j + r nb/R,
+// output index (j / Ns) Ns R + j % Ns + r Ns); TB holds the nb-th roots,
+// TW the n-th roots.  last: Ns R = nb, the pass ends in the pixel stores.
+template <int R>
+__device__ __attribute__((always_inline)) inline void blue_pass(float2 *X, float2 *Y,
+                                                                const float2 *TW,
+                                                                const float2 *TB, int L,
+                                                                int Ns, int sign, int in,
+                                                                bool last, const BlueRing &br)
+{
+    typedef float2 C;
+    constexpr int NT = kBlueThreads;
+    constexpr int MAXQ = 1;   // the plan admits nb / R <= NT
+    const int nbf = L / R;
+    const int tstep0 = L / (Ns * R);
+    const unsigned magic = (unsigned)((0x100000000ull + (unsigned)Ns - 1) / (unsigned)Ns);
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    C a[MAXQ][R], b[MAXQ][R];
+    if (in == kBlueInBq) {
+        // the kernel spectrum's global loads go out before the LDS reads
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+            const int j = tid + q * NT;
+            if (j < nbf) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) a[q][r] = cvt<C>(br.bq[j + r * nbf]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) {
+        const int j = tid + q * NT;
+        if (j < nbf) {
+            if (in == kBlueInZ) {
+                const int h = br.h;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int k = j + r * nbf;
+                    C ae = cplx<C>(0.0, 0.0), ao = ae;
+                    if (k < br.len) {
+                        // Z_t = (F_t + conj F_{h-t}) + i e^{2 pi i t/n} (F_t - conj F_{h-t}),
+                        // t = 2k and 2k + 1
+                        const int t0 = 2 * k, t1 = t0 + 1;
+                        const C F0 = X[PadIdx::at(t0)], G0 = X[PadIdx::at(h - t0)];
+                        const C F1 = X[PadIdx::at(t1)], G1 = X[PadIdx::at(h - t1)];
+                        const C z0 = cadd(cadd(F0, conjd(G0)),
+                                          muli(cmul(tw_at(TW, t0), csub(F0, conjd(G0))), +1));
+                        const C z1 = cadd(cadd(F1, conjd(G1)),
+                                          muli(cmul(tw_at(TW, t1), csub(F1, conjd(G1))), +1));
+                        const int e = (int)(((unsigned)k * (unsigned)k) % (unsigned)h);
+                        const C c = tw_at(TW, 2 * e);
+                        ae = cmul(z0, c);
+                        ao = cmul(z1, c);
+                    }
+                    a[q][r] = ae;
+                    b[q][r] = ao;
+                }
+            } else if (in == kBlueInBq) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int k = PadIdx::at(j + r * nbf);
+                    const C w = a[q][r];
+                    a[q][r] = cmul(X[k], w);
+                    b[q][r] = cmul(Y[k], w);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int k = PadIdx::at(j + r * nbf);
+                    a[q][r] = X[k];
+                    b[q][r] = Y[k];
+                }
+            }
+            if (Ns > 1) {
+                const int jq = (int)__umulhi((unsigned)j, magic);
+                const int ts = tstep0 * (j - jq * Ns);
+                if (ts != 0) {
+                    C w1 = tw_at(TB, ts);
+                    if (sign < 0) w1.y = -w1.y;
+                    C wr = w1;
+#pragma unroll
+                    for (int r = 1; r < R; ++r) {
+                        a[q][r] = cmul(a[q][r], wr);
+                        b[q][r] = cmul(b[q][r], wr);
+                        wr = cmul(wr, w1);
+                    }
+                }
+            }
+            small_dft<R, C>(a[q], sign);
+            small_dft<R, C>(b[q], sign);
+        }
+    }
+    if (last) {
+        // j < Ns: outputs o = j + r nbf; for o < len, E_o = c_o a, O_o = c_o b
+        const int h = br.h, len = br.len;
+        double *out = br.out;
+        const bool al = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+        double2 *o2 = reinterpret_cast<double2 *>(out);
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+            const int j = tid + q * NT;
+            if (j < nbf) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int o = j + r * nbf;
+                    if (o < len) {
+                        const int e = (int)(((unsigned)o * (unsigned)o) % (unsigned)h);
+                        const C c = tw_at(TW, 2 * e);
+                        const C E = cmul(a[q][r], c);
+                        const C t = cmul(tw_at(TW, 2 * o), cmul(b[q][r], c));
+                        const double2 z0 = todbl(cadd(E, t)), z1 = todbl(csub(E, t));
+                        if (al) {
+                            o2[o] = z0;
+                            o2[o + len] = z1;
+                        } else {
+                            out[2 * o] = z0.x;
+                            out[2 * o + 1] = z0.y;
+                            out[2 * (o + len)] = z1.x;
+                            out[2 * (o + len) + 1] = z1.y;
+                        }
+                    }
+                }
+            }
+        }
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+            const int j = tid + q * NT;
+            if (j < nbf) {
+                const int jq = (Ns == 1) ? j : (int)__umulhi((unsigned)j, magic);
+                const int base = jq * Ns * R + (j - jq * Ns);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int k = PadIdx::at(base + r * Ns);
+                    X[k] = a[q][r];
+                    Y[k] = b[q][r];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// The two convolutions of a Bluestein fast-path ring (after the fold):
+// forward passes (sign -1), then inverse passes (sign +1).
+__device__ __attribute__((always_inline)) inline void blue_fft(float2 *X, float2 *Y,
+                                                               const float2 *TW,
+                                                               const float2 *TB,
+                                                               const RingDesc &d,
+                                                               const BlueRing &br)
+{
+    const int L = d.nb;
+    int Ns = 1;
+    for (int s = 0; s < 2 * d.np; ++s) {
+        const int p = (s < d.np) ? s : s - d.np;
+        const int R = (int)((d.rads >> (5 * p)) & 31);
+        if (p == 0) Ns = 1;
+        const int sign = (s < d.np) ? -1 : +1;
+        const int in = (s == 0) ? kBlueInZ : (s == d.np ? kBlueInBq : kBlueInBuf);
+        const bool last = s == 2 * d.np - 1;
+        switch (R) {
+        case 8: blue_pass<8>(X, Y, TW, TB, L, Ns, sign, in, last, br); break;
+        case 4: blue_pass<4>(X, Y, TW, TB, L, Ns, sign, in, last, br); break;
+        case 2: blue_pass<2>(X, Y, TW, TB, L, Ns, sign, in, last, br); break;
+        case 7: blue_pass<7>(X, Y, TW, TB, L, Ns, sign, in, last, br); break;
+        case 5: blue_pass<5>(X, Y, TW, TB, L, Ns, sign, in, last, br); break;
+        default: blue_pass<3>(X, Y, TW, TB, L, Ns, sign, in, last, br); break;
+        }
+        Ns *= R;
+    }
+}
+
+// Persistent like k_ring_synth_fast (XCD ranges, next ring's modes loaded
+// before the current ring's passes); complex64 Delta only.
+__global__ __launch_bounds__(kBlueThreads, 4) void k_ring_synth_blue(
+    const int *__restrict__ ids, int count, int nmaps, const RingDesc *__restrict__ rings,
+    const double2 *__restrict__ pool, const float2 *__restrict__ delta,
+    const int *__restrict__ minv, int mcontig, int mmax, int nm, int nrings,
+    double *__restrict__ map, long long npix, RingLds lds)
+{
+    typedef float2 C;
+    extern __shared__ double2 lds_raw[];
+    C *X = reinterpret_cast<C *>(lds_raw);
+    C *Y = X + lds.fft_entries;
+    C *TW = Y + lds.y_entries;
+    C *TB = TW + lds.tw_entries;
+    const long long total = (long long)count * nmaps;
+    const int per = (int)(gridDim.x / 8);
+    const int x = (int)(blockIdx.x % 8), w = (int)(blockIdx.x / 8);
+    const long long hi = total * (x + 1) / 8;
+    long long it = total * x / 8 + w;
+    if (it >= hi) return;
+    int i, bi;
+    ring_item(it, count, i, bi);
+    long long b = bi;
+    int r = ids[i];
+    FastModes<kBlueThreads, float2> raw;
+    load_fast<kBlueThreads>(raw, delta + b * nm * nrings + r, nrings, minv, mcontig, mmax);
+    for (bool first = true;; first = false) {
+        const RingDesc d = rings[r];
+        BlueRing br;
+        br.h = d.n / 2;
+        br.len = br.h / 2;
+        br.bq = pool + d.bq;
+        br.out = map + b * npix + d.start;
+        if (!first) __syncthreads();   // the previous ring's last pass has read TW
+        load_tw<kBlueThreads>(TW, pool + d.tw, d.n);
+        load_tw<kBlueThreads>(TB, pool + d.twb, d.nb);
+        fold_fast<kBlueThreads>(X, d, raw, mmax);
+        const long long nx = it + per;
+        if (nx < hi) {
+            ring_item(nx, count, i, bi);
+            b = bi;
+            r = ids[i];
+            load_fast<kBlueThreads>(raw, delta + b * nm * nrings + r, nrings, minv, mcontig,
+                                    mmax);
+        }
+        blue_fft(X, Y, TW, TB, d, br);
+        if (nx >= hi) break;
+        it = nx;
+    }
 }
 
 template <int NT, int MAXN, typename DT>
@@ -1196,12 +1499,12 @@ hipError_t synth_fast_class(const sht_plan_s *p, const DT *delta, double *map, h
 {
     const RingClass &rc = p->scls[kFastClass];
     if (rc.count == 0) return hipSuccess;
-    const size_t lds = (size_t)rc.lds.total() * sizeof(double2);
+    const size_t lds = (size_t)rc.lds.total() * sizeof(typename FastPrec<DT>::C);
     hipError_t e = set_lds((const void *)k_ring_synth_fast<DT>, lds);
     if (e != hipSuccess) return e;
-    // two workgroups per CU (the LDS of a ring), a multiple of 8
+    // as many workgroups per CU as the LDS of a ring allows (2 or 4), a multiple of 8
     const long long items = (long long)rc.count * p->nmaps;
-    long long grid = 2LL * (p->num_cus > 0 ? p->num_cus : 256);
+    long long grid = (long long)FastPrec<DT>::kBlocks * (p->num_cus > 0 ? p->num_cus : 256);
     if (grid > items) grid = items;
     grid = ((grid + 7) / 8) * 8;
     hipLaunchKernelGGL((k_ring_synth_fast<DT>), dim3((unsigned)grid), dim3(kFastThreads), lds,
@@ -1210,12 +1513,39 @@ hipError_t synth_fast_class(const sht_plan_s *p, const DT *delta, double *map, h
     return hipGetLastError();
 }
 
-// The fast-path kernel (LDS-bound at two workgroups per CU) and the
-// size-class kernels write disjoint rings.  For large plans the fast path
-// runs on the plan's auxiliary stream beside the others (forked from and
-// joined back into the caller's stream by events, so the call stays ordered
-// on `st` and capturable): their workgroups then share the CUs and fill each
-// other's tails (10.6 -> 10.2 ms for 16 maps at l_max 4096 / nside 2048).
+// The Bluestein fast path (complex64 Delta only): two 512-thread
+// workgroups per CU, persistent.
+hipError_t synth_blue_class(const sht_plan_s *p, const float2 *delta, double *map,
+                            hipStream_t st)
+{
+    const RingClass &rc = p->scls[kBlueClass];
+    if (rc.count == 0) return hipSuccess;
+    const size_t lds = (size_t)rc.lds.total() * sizeof(float2);
+    hipError_t e = set_lds((const void *)k_ring_synth_blue, lds);
+    if (e != hipSuccess) return e;
+    const long long items = (long long)rc.count * p->nmaps;
+    long long grid = 2LL * (p->num_cus > 0 ? p->num_cus : 256);
+    if (grid > items) grid = items;
+    grid = ((grid + 7) / 8) * 8;
+    hipLaunchKernelGGL(k_ring_synth_blue, dim3((unsigned)grid), dim3(kBlueThreads), lds, st,
+                       rc.d_ids, rc.count, p->nmaps, p->d_rings, p->d_pool, delta, p->d_minv,
+                       p->mcontig, p->mmax, p->nm, p->nrings, map, p->npix, rc.lds);
+    return hipGetLastError();
+}
+
+hipError_t synth_blue_class(const sht_plan_s *p, const double2 *, double *, hipStream_t)
+{
+    // FP64 plans put no ring in this class
+    return p->scls[kBlueClass].count == 0 ? hipSuccess : hipErrorInvalidConfiguration;
+}
+
+// The fast-path kernel (LDS-bound at two or three workgroups per CU), the
+// Bluestein fast path and the size-class kernels write disjoint rings.  For
+// large plans the fast path runs on the plan's auxiliary stream beside the
+// others (forked from and joined back into the caller's stream by events, so
+// the call stays ordered on `st` and capturable): their workgroups then
+// share the CUs and fill each other's tails (FP64 size classes: 10.6 -> 10.2
+// ms for 16 maps at l_max 4096 / nside 2048; Bluestein fast path: 8.2 -> 8.0).
 // Small plans launch everything on `st` (a fork costs microseconds).
 constexpr long long kForkItems = 4096;
 
@@ -1223,7 +1553,8 @@ template <typename DT>
 static hipError_t ring_synth_dt(const sht_plan_s *p, const DT *delta, double *map, hipStream_t st)
 {
     const long long fast = (long long)p->scls[kFastClass].count * p->nmaps;
-    const long long rest = (long long)(p->scls[0].count + p->scls[1].count + p->scls[2].count) *
+    const long long rest = (long long)(p->scls[0].count + p->scls[1].count + p->scls[2].count +
+                                       p->scls[kBlueClass].count) *
                            p->nmaps;
     const bool fork = p->aux_stream && fast > 0 && rest > 0 && fast + rest >= kForkItems;
     // the fork and join events belong to the plan: calls from several host
@@ -1236,6 +1567,7 @@ static hipError_t ring_synth_dt(const sht_plan_s *p, const DT *delta, double *ma
         if (e == hipSuccess) e = hipStreamWaitEvent(p->aux_stream, p->ev_fork, 0);
     }
     if (e == hipSuccess) e = synth_fast_class<DT>(p, delta, map, fork ? p->aux_stream : st);
+    if (e == hipSuccess) e = synth_blue_class(p, delta, map, st);
     if (e == hipSuccess) e = synth_class<1024, 8192, DT>(p, 2, delta, map, st);
     if (e == hipSuccess) e = synth_class<512, 4096, DT>(p, 1, delta, map, st);
     if (e == hipSuccess) e = synth_class<256, 2048, DT>(p, 0, delta, map, st);

@@ -52,15 +52,17 @@ struct PairDesc {
 
 // Rings grouped by FFT length for the Fourier kernels (LDS and register
 // budgets differ per class): class 0 up to 2048 points, 1 up to 4096, 2 up to 8192.
-// LDS of a ring-class workgroup, in double2 entries: the spectrum / FFT
-// buffer (which also stages partial alias sums during the fold), and the
+// LDS of a ring-class workgroup, in complex entries: the spectrum / FFT
+// buffer (which also stages partial alias sums during the fold), the second
+// convolution buffer of the Bluestein fast path (y, 0 elsewhere), and the
 // two-level twiddle tables of the ring length (tw) and of the Bluestein
-// length (tb).
+// length (tb), in that order.
 struct RingLds {
     int fft_entries;
     int tw_entries;
     int tb_entries;
-    int total() const { return fft_entries + tw_entries + tb_entries; }
+    int y_entries;
+    int total() const { return fft_entries + y_entries + tw_entries + tb_entries; }
 };
 
 struct RingClass {
@@ -74,11 +76,18 @@ constexpr int kClassThreads[kNumRingClasses] = {256, 512, 1024};
 // fast path, plus one class for the fast path: even rings whose half length
 // is 7-smooth and at most kFastMaxH, run by kFastThreads-thread workgroups
 // with register-held radix-16/8/4/2/7/5/3 butterflies on a padded LDS buffer.
+// Mixed-form plans (complex64 Delta) add a Bluestein fast path: even rings
+// whose half length h = 2 len has a len that is not 7-smooth, with a
+// convolution length nb <= kBlueMaxN, run by kBlueThreads-thread workgroups
+// that take the even- and odd-indexed convolutions side by side.
 constexpr int kFastClass = 3;
-constexpr int kNumSynthClasses = 4;
+constexpr int kBlueClass = 4;
+constexpr int kNumSynthClasses = 5;
 constexpr int kFastThreads = 256;
 constexpr int kFastMaxH = 4096;
 constexpr int kFastMaxModes = 17 * kFastThreads;   // the fold holds m < 4352 in registers
+constexpr int kBlueThreads = 512;
+constexpr int kBlueMaxN = 4096;
 // padded LDS index of the fast path (one spare entry per 16)
 inline int fast_pad(int i) { return i + (i >> 4); }
 // butterflies per thread a fast pass of radix R holds in registers (at most
@@ -110,6 +119,49 @@ inline int fast_radices(int h, unsigned long long *rads)
         *rads |= (unsigned long long)rad[p] << (5 * p);
     }
     return np;
+}
+
+// Radices of the Bluestein fast path for a convolution length nb (7-smooth,
+// 1 < nb <= kBlueMaxN): as many 8s as possible, then 4, 2, 7, 5, 3.  Every
+// pass holds at most one butterfly per thread (nb / R <= kBlueThreads).
+// Returns the number of passes, 0 if nb is not eligible.
+inline int blue_radices(int nb, unsigned long long *rads)
+{
+    int rad[12];
+    if (nb < 2 || nb > kBlueMaxN) return 0;
+    int np = 0, r = nb;
+    while (r % 8 == 0 && np < 12) { rad[np++] = 8; r /= 8; }
+    if (r % 4 == 0 && np < 12) { rad[np++] = 4; r /= 4; }
+    if (r % 2 == 0 && np < 12) { rad[np++] = 2; r /= 2; }
+    for (int f : {7, 5, 3})
+        while (r % f == 0 && np < 12) { rad[np++] = f; r /= f; }
+    if (r != 1) return 0;
+    *rads = 0;
+    for (int p = 0; p < np; ++p) {
+        if (nb / rad[p] > kBlueThreads) return 0;
+        *rads |= (unsigned long long)rad[p] << (5 * p);
+    }
+    return np;
+}
+
+// Grows the Bluestein fast class layout by one ring of n pixels and
+// convolution length nb for modes 0..mmax: the first buffer holds the phased
+// modes, the spectrum and the alias staging, then the even-indexed
+// convolution; the second the odd-indexed one; then the twiddle tables of
+// n and nb.
+inline void blue_lds_add(RingLds &l, int n, int nb, int mmax)
+{
+    int top = n / 2 > kBlueThreads - 1 ? n / 2 : kBlueThreads - 1;
+    top = top > mmax ? top : mmax;
+    top = top > nb - 1 ? top : nb - 1;
+    const int need = fast_pad(top) + 1;
+    l.fft_entries = l.fft_entries > need ? l.fft_entries : need;
+    const int y = fast_pad(nb - 1) + 1;
+    l.y_entries = l.y_entries > y ? l.y_entries : y;
+    const int tw = 64 + (n + 63) / 64;
+    l.tw_entries = l.tw_entries > tw ? l.tw_entries : tw;
+    const int tb = 64 + (nb + 63) / 64;
+    l.tb_entries = l.tb_entries > tb ? l.tb_entries : tb;
 }
 
 // Grows the fast class layout by one ring of n pixels (n even, fast path)

@@ -77,6 +77,35 @@ int best_smooth7(long long L)
     return pick;
 }
 
+// Convolution length of the Bluestein fast path for a convolution of L
+// points: the cheapest by the same per-pass costs among the lengths in
+// [L, min(1.3 L, kBlueMaxN)] whose radix list holds one butterfly per thread
+// in every pass; 0 if there is none.
+int best_blue_nb(long long L)
+{
+    double best = 1e300;
+    int pick = 0;
+    for (long long c = L; c <= sht::kBlueMaxN && c <= (L * 13) / 10 + 1; ++c) {
+        unsigned long long rads = 0;
+        const int np = smooth7(c) ? sht::blue_radices((int)c, &rads) : 0;
+        if (np == 0) continue;
+        double cost = 0.0;
+        for (int q = 0; q < np; ++q) {
+            switch ((int)((rads >> (5 * q)) & 31)) {
+            case 8: cost += 12 + 10; break;
+            case 4: cost += 8.5 + 10; break;
+            case 2: cost += 5 + 10; break;
+            case 3: cost += 8 + 10; break;
+            case 5: cost += 13 + 10; break;
+            default: cost += 17 + 10; break;
+            }
+        }
+        cost *= (double)c;
+        if (cost < best) { best = cost; pick = (int)c; }
+    }
+    return pick;
+}
+
 uint64_t bits(double d)
 {
     uint64_t u;
@@ -374,6 +403,8 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     std::vector<int> ring_class(R), ring_sclass(R);
     sht::RingLds class_lds[sht::kNumRingClasses] = {};
     sht::RingLds sclass_lds[sht::kNumSynthClasses] = {};
+    // the Bluestein fast path takes complex64 Delta (the mixed forms)
+    const bool blue_ok = d->precision != SHT_FP64 && mval.back() < sht::kFastMaxModes;
     for (int r = 0; r < R; ++r) {
         const long long n = d->nphi[r];
         RingDesc &g = rings[r];
@@ -385,14 +416,27 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
         g.tw = g.tch = g.twb = g.bq = -1;
         const int spec = (n % 2 == 0) ? g.clen + 1 : g.clen;  // F_k entries
         int fftlen;
+        unsigned long long fr = 0;
         if (smooth7(g.clen) && g.clen <= 8192) {
             g.nb = 0;
             fftlen = g.clen;
+            // an even ring of 7-smooth half length that the fast path cannot
+            // take (a pass would hold too many butterflies per thread) joins
+            // the Bluestein fast path
+            if (blue_ok && n % 2 == 0 && g.clen % 2 == 0 && sht::fast_radices(g.clen, &fr) == 0) {
+                const int nbb = best_blue_nb((long long)g.clen - 1);
+                if (nbb > 0) {
+                    g.half = 1;
+                    g.nb = nbb;
+                    fftlen = nbb;
+                }
+            }
         } else if (n % 2 == 0 && g.clen % 2 == 0) {
             // split into the even- and odd-indexed halves: Bluestein of
             // length clen / 2 needs a convolution of only clen - 1 points
             g.half = 1;
-            g.nb = best_smooth7((long long)g.clen - 1);
+            const int nbb = blue_ok ? best_blue_nb((long long)g.clen - 1) : 0;
+            g.nb = nbb > 0 ? nbb : best_smooth7((long long)g.clen - 1);
             if (g.nb > 8192) return SHT_ERR_UNSUPPORTED;
             fftlen = g.nb;
         } else {
@@ -406,9 +450,13 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
         sht::ring_lds_add(class_lds[c], c, g.n, g.nb, need);
         g.np = (n % 2 == 0 && g.nb == 0 && mval.back() < sht::kFastMaxModes)
                    ? sht::fast_radices(g.clen, &g.rads) : 0;
-        if (g.np > 0) {
+        if (g.np == 0 && g.half && blue_ok) g.np = sht::blue_radices(g.nb, &g.rads);
+        if (g.np > 0 && g.nb == 0) {
             ring_sclass[r] = sht::kFastClass;
             sht::fast_lds_add(sclass_lds[sht::kFastClass], g.n, mval.back());
+        } else if (g.np > 0) {
+            ring_sclass[r] = sht::kBlueClass;
+            sht::blue_lds_add(sclass_lds[sht::kBlueClass], g.n, g.nb, mval.back());
         } else {
             ring_sclass[r] = c;
             sht::ring_lds_add(sclass_lds[c], c, g.n, g.nb, need);
@@ -650,19 +698,21 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
         static const char *kPrec[] = {"fp64", "fp32_mfma", "bf16x3_mfma", "f16x2_mfma"};
         int nblue = 0, nfast = 0;
         for (int r = 0; r < R; ++r) {
-            nblue += rings[r].nb != 0;
-            nfast += rings[r].np > 0;
+            nblue += rings[r].nb != 0 && ring_sclass[r] != sht::kBlueClass;
+            nfast += ring_sclass[r] == sht::kFastClass;
         }
         sht::log_line("plan l_max=%d nm=%d m_max=%d rings=%d pairs=%d maps=%d precision=%s "
                       "delta=%s", p->lmax, p->nm, p->mmax, R, p->npairs, p->nmaps,
                       kPrec[p->precision], delta_f32(p) ? "complex64" : "complex128");
-        sht::log_line("plan synthesis rings: fast path %d (Stockham in registers), size classes "
-                      "%d / %d / %d (256 / 512 / 1024 threads), of which Bluestein %d",
-                      nfast, p->scls[0].count, p->scls[1].count, p->scls[2].count, nblue);
+        sht::log_line("plan synthesis rings: fast path %d (Stockham in registers), Bluestein "
+                      "fast path %d, size classes %d / %d / %d (256 / 512 / 1024 threads), of "
+                      "which Bluestein %d",
+                      nfast, p->scls[sht::kBlueClass].count, p->scls[0].count,
+                      p->scls[1].count, p->scls[2].count, nblue);
         // the radix lists of the three longest fast-path ring lengths
         std::map<int, int> longest;   // nphi -> a ring of that length
         for (int r = 0; r < R; ++r)
-            if (rings[r].np > 0) longest[-rings[r].n] = r;
+            if (ring_sclass[r] == sht::kFastClass) longest[-rings[r].n] = r;
         int shown = 0;
         for (const auto &kv : longest) {
             if (shown++ == 3) break;

@@ -134,3 +134,46 @@ def test_mixed_coefficient_range(P, prec):
         em = ref.alm2map(lmax, g, alms[i])
         assert np.all(np.isfinite(mp[i])), i
         assert _rel(mp[i], em) < TOL, i
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixed_bluestein_fast_rings(P, prec):
+    """Rings of 4 i pixels with i not 7-smooth take the mixed forms' complex64
+    Bluestein path (even- and odd-indexed convolutions side by side, lengths
+    21 to 4096): from heavy aliasing (44 pixels at m_max 4096) to rings longer
+    than m_max, beside 7-smooth and odd rings, at odd pixel offsets (unaligned
+    stores), ring by ring against the oracle."""
+    _say("mixed Bluestein fast-path rings", prec)
+    L, N = 4096, 2048
+    g0 = W.healpix_geometry(N)
+    # north-cap ring i - 1 has 4 i pixels; 2048 and 1536 are 7-smooth, the
+    # equator ring 2 N - 1 has 4 N
+    ivals = [11, 13, 22, 97, 509, 1021, 1023, 1031, 2039, 2047, 2048, 1536]
+    rings = [i - 1 for i in ivals] + [2 * N - 1]
+    # plus an odd ring, and 7560 pixels: half length 3780 = 4 x 7 x 5 x 27 is
+    # 7-smooth, but its radix-7 pass would need three butterflies per thread
+    # on the fast path, so the mixed forms take it through Bluestein
+    nphi = np.array([int(g0.nphi[r]) for r in rings] + [4093, 7560], np.int64)
+    cth = np.append(g0.cth[rings], [0.3, -0.55])
+    sth = np.sqrt(1.0 - cth * cth)
+    phi0 = np.append(g0.phi0[rings], [0.1, 0.0])
+    start = np.concatenate([[1], 1 + np.cumsum(nphi[:-1] + 1)]).astype(np.int64)
+    g = W.Geometry(cth, sth, phi0, nphi, start, int(start[-1] + nphi[-1]), "bluestein rings")
+    nmaps = 2
+    alms = np.stack([W.random_alm(L, [306, i]) for i in range(nmaps)])
+    plan = P.Plan(L, g, nmaps=nmaps, precision=prec)
+    out = plan.alm2map(torch.from_numpy(alms).to(_dev())).cpu().numpy()
+    for i in range(nmaps):
+        exp = ref.alm2map_rings(L, g, alms[i], list(range(len(nphi))))
+        num = den = 0.0
+        for r, e in enumerate(exp):
+            got = out[i, start[r]:start[r] + nphi[r]]
+            assert _rel(got, e) < 4 * TOL, (i, r, int(nphi[r]))
+            num += float(np.sum((got - e) ** 2))
+            den += float(np.sum(e ** 2))
+        assert np.sqrt(num / den) < TOL, i
+        # the gaps between the rings stay untouched
+        gaps = np.ones(out.shape[1], bool)
+        for r in range(len(nphi)):
+            gaps[start[r]:start[r] + nphi[r]] = False
+        assert np.all(out[i, gaps] == 0.0), i
