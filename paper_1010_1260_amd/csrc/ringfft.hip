@@ -830,7 +830,12 @@ struct FastModes {
     DT v[Q];   // as stored (complex64 or complex128), widened at use
 };
 
-// Loads of the fold: modes m = tid + q NT of one ring (issued together).
+// Loads of the fold: modes m = tid + q NT of one ring.  Each load waits for
+// the one before it: the loads of all workgroups then move through the m
+// rows of Delta together, so the DRAM rows they open serve the neighbouring
+// rings too.  Issued all at once they reach DRAM as a burst over thousands
+// of rows, which measured 17% slower (split-FP16 belt rings, 16 maps at
+// l_max 4096 / nside 2048: 3.43 ms paced, 4.00 ms as a burst).
 template <int NT, typename DT>
 __device__ __attribute__((always_inline)) inline void load_fast(FastModes<NT, DT> &raw,
                                                                 const DT *__restrict__ drow,
@@ -839,12 +844,31 @@ __device__ __attribute__((always_inline)) inline void load_fast(FastModes<NT, DT
                                                                 int mcontig, int mmax)
 {
     constexpr int QM = FastModes<NT, DT>::Q;
-    const int tid = threadIdx.x;
+    // an opaque thread index keeps the per-q addresses from being hoisted
+    // out of the persistent kernels' ring loop (where they would stay live)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    if (mcontig) {
 #pragma unroll
-    for (int q = 0; q < QM; ++q) {
-        const int m = tid + q * NT;
-        const int i = (m <= mmax) ? (mcontig ? m : minv[m]) : -1;
-        raw.v[q] = (i >= 0) ? drow[(long long)i * dstride] : DT{};
+        for (int q = 0; q < QM; ++q) {
+            const int m = tid + q * NT;
+            raw.v[q] = (m <= mmax) ? drow[(long long)m * dstride] : DT{};
+            // s_waitcnt vmcnt(0) expcnt(7) lgkmcnt(15)
+            if (q + 1 < QM) __builtin_amdgcn_s_waitcnt(0x0F70);
+        }
+    } else {
+        // every position lookup first, then the loads
+        int pos[QM];
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            const int m = tid + q * NT;
+            pos[q] = (m <= mmax) ? minv[m] : -1;
+        }
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            raw.v[q] = (pos[q] >= 0) ? drow[(long long)pos[q] * dstride] : DT{};
+            if (q + 1 < QM) __builtin_amdgcn_s_waitcnt(0x0F70);
+        }
     }
 }
 
@@ -1085,12 +1109,12 @@ struct BlueRing {
 // One pass of radix R over both nb-point buffers (input index j + r nb/R,
 // output index (j / Ns) Ns R + j % Ns + r Ns); TB holds the nb-th roots,
 // TW the n-th roots.  last: Ns R = nb, the pass ends in the pixel stores.
-template <int R>
+template <int R, int sign>
 __device__ __attribute__((always_inline)) inline void blue_pass(float2 *X, float2 *Y,
                                                                 const float2 *TW,
                                                                 const float2 *TB, int L,
-                                                                int Ns, int sign, int in,
-                                                                bool last, const BlueRing &br)
+                                                                int Ns, int in, bool last,
+                                                                const BlueRing &br)
 {
     typedef float2 C;
     constexpr int NT = kBlueThreads;
@@ -1227,9 +1251,11 @@ __device__ __attribute__((always_inline)) inline void blue_pass(float2 *X, float
     }
 }
 
-// The two convolutions of a Bluestein fast-path ring (after the fold):
-// forward passes (sign -1), then inverse passes (sign +1).
-__device__ __attribute__((always_inline)) inline void blue_fft(float2 *X, float2 *Y,
+// The passes of one direction of a Bluestein fast-path ring's two
+// convolutions: sign -1 (forward, from the folded spectrum) or +1 (inverse,
+// ending in the pixel stores).
+template <int sign>
+__device__ __attribute__((always_inline)) inline void blue_dir(float2 *X, float2 *Y,
                                                                const float2 *TW,
                                                                const float2 *TB,
                                                                const RingDesc &d,
@@ -1237,20 +1263,17 @@ __device__ __attribute__((always_inline)) inline void blue_fft(float2 *X, float2
 {
     const int L = d.nb;
     int Ns = 1;
-    for (int s = 0; s < 2 * d.np; ++s) {
-        const int p = (s < d.np) ? s : s - d.np;
+    for (int p = 0; p < d.np; ++p) {
         const int R = (int)((d.rads >> (5 * p)) & 31);
-        if (p == 0) Ns = 1;
-        const int sign = (s < d.np) ? -1 : +1;
-        const int in = (s == 0) ? kBlueInZ : (s == d.np ? kBlueInBq : kBlueInBuf);
-        const bool last = s == 2 * d.np - 1;
+        const int in = (p > 0) ? kBlueInBuf : (sign < 0 ? kBlueInZ : kBlueInBq);
+        const bool last = sign > 0 && p == d.np - 1;
         switch (R) {
-        case 8: blue_pass<8>(X, Y, TW, TB, L, Ns, sign, in, last, br); break;
-        case 4: blue_pass<4>(X, Y, TW, TB, L, Ns, sign, in, last, br); break;
-        case 2: blue_pass<2>(X, Y, TW, TB, L, Ns, sign, in, last, br); break;
-        case 7: blue_pass<7>(X, Y, TW, TB, L, Ns, sign, in, last, br); break;
-        case 5: blue_pass<5>(X, Y, TW, TB, L, Ns, sign, in, last, br); break;
-        default: blue_pass<3>(X, Y, TW, TB, L, Ns, sign, in, last, br); break;
+        case 8: blue_pass<8, sign>(X, Y, TW, TB, L, Ns, in, last, br); break;
+        case 4: blue_pass<4, sign>(X, Y, TW, TB, L, Ns, in, last, br); break;
+        case 2: blue_pass<2, sign>(X, Y, TW, TB, L, Ns, in, last, br); break;
+        case 7: blue_pass<7, sign>(X, Y, TW, TB, L, Ns, in, last, br); break;
+        case 5: blue_pass<5, sign>(X, Y, TW, TB, L, Ns, in, last, br); break;
+        default: blue_pass<3, sign>(X, Y, TW, TB, L, Ns, in, last, br); break;
         }
         Ns *= R;
     }
@@ -1301,7 +1324,8 @@ __global__ __launch_bounds__(kBlueThreads, 4) void k_ring_synth_blue(
             load_fast<kBlueThreads>(raw, delta + b * nm * nrings + r, nrings, minv, mcontig,
                                     mmax);
         }
-        blue_fft(X, Y, TW, TB, d, br);
+        blue_dir<-1>(X, Y, TW, TB, d, br);
+        blue_dir<+1>(X, Y, TW, TB, d, br);
         if (nx >= hi) break;
         it = nx;
     }
@@ -1458,9 +1482,9 @@ hipError_t set_lds(const void *fn, size_t bytes)
 }
 
 template <int NT, int MAXN, typename DT>
-hipError_t synth_class(const sht_plan_s *p, int c, const DT *delta, double *map, hipStream_t st)
+hipError_t synth_class(const sht_plan_s *p, const RingClass &rc, const DT *delta, double *map,
+                       hipStream_t st)
 {
-    const RingClass &rc = p->scls[c];
     if (rc.count == 0) return hipSuccess;
     const size_t lds = (size_t)rc.lds.total() * sizeof(double2);
     hipError_t e = set_lds((const void *)k_ring_synth<NT, MAXN, DT>, lds);
@@ -1533,10 +1557,15 @@ hipError_t synth_blue_class(const sht_plan_s *p, const float2 *delta, double *ma
     return hipGetLastError();
 }
 
-hipError_t synth_blue_class(const sht_plan_s *p, const double2 *, double *, hipStream_t)
+// complex128 Delta (FP64 plans have no ring in the class; a mixed-form plan
+// given a caller's complex128 Delta): the class's rings by size class.
+hipError_t synth_blue_class(const sht_plan_s *p, const double2 *delta, double *map,
+                            hipStream_t st)
 {
-    // FP64 plans put no ring in this class
-    return p->scls[kBlueClass].count == 0 ? hipSuccess : hipErrorInvalidConfiguration;
+    hipError_t e = synth_class<1024, 8192, double2>(p, p->bcls[2], delta, map, st);
+    if (e == hipSuccess) e = synth_class<512, 4096, double2>(p, p->bcls[1], delta, map, st);
+    if (e == hipSuccess) e = synth_class<256, 2048, double2>(p, p->bcls[0], delta, map, st);
+    return e;
 }
 
 // The fast-path kernel (LDS-bound at two or three workgroups per CU), the
@@ -1568,9 +1597,9 @@ static hipError_t ring_synth_dt(const sht_plan_s *p, const DT *delta, double *ma
     }
     if (e == hipSuccess) e = synth_fast_class<DT>(p, delta, map, fork ? p->aux_stream : st);
     if (e == hipSuccess) e = synth_blue_class(p, delta, map, st);
-    if (e == hipSuccess) e = synth_class<1024, 8192, DT>(p, 2, delta, map, st);
-    if (e == hipSuccess) e = synth_class<512, 4096, DT>(p, 1, delta, map, st);
-    if (e == hipSuccess) e = synth_class<256, 2048, DT>(p, 0, delta, map, st);
+    if (e == hipSuccess) e = synth_class<1024, 8192, DT>(p, p->scls[2], delta, map, st);
+    if (e == hipSuccess) e = synth_class<512, 4096, DT>(p, p->scls[1], delta, map, st);
+    if (e == hipSuccess) e = synth_class<256, 2048, DT>(p, p->scls[0], delta, map, st);
     if (fork) {
         // join even after a failed launch, so that `st` never runs ahead of
         // work already queued on the auxiliary stream

@@ -266,6 +266,9 @@ struct sht_plan_s {
     std::vector<int> ring_nb;     // Bluestein length of each ring (0: none)
     sht::RingClass cls[sht::kNumRingClasses];     // analysis: every ring
     sht::RingClass scls[sht::kNumSynthClasses];   // synthesis
+    // the Bluestein fast path's rings by size class, for synthesis from a
+    // caller's complex128 Delta (sht_delta2map), which that path does not take
+    sht::RingClass bcls[sht::kNumRingClasses];
     std::vector<int> ring_sclass;  // synthesis class of each ring
     int fwd_chains;      // ring pairs per lane of the FP64 forward Legendre kernel (1, 2, 4)
     int num_cus;         // compute units of the plan's device

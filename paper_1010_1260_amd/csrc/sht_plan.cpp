@@ -179,6 +179,8 @@ void free_tables(sht_plan_s *p)
     for (int c = 0; c < sht::kNumRingClasses; ++c) {
         if (p->cls[c].d_ids) (void)hipFree(p->cls[c].d_ids);
         p->cls[c].d_ids = nullptr;
+        if (p->bcls[c].d_ids) (void)hipFree(p->bcls[c].d_ids);
+        p->bcls[c].d_ids = nullptr;
     }
     p->d_pairs = nullptr; p->d_mval = nullptr; p->d_moff = nullptr; p->d_mu = nullptr;
     p->d_A = nullptr; p->d_cn = nullptr; p->d_minv = nullptr; p->d_rings = nullptr;
@@ -403,6 +405,8 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
     std::vector<int> ring_class(R), ring_sclass(R);
     sht::RingLds class_lds[sht::kNumRingClasses] = {};
     sht::RingLds sclass_lds[sht::kNumSynthClasses] = {};
+    std::vector<int> ring_bclass(R, -1);
+    sht::RingLds bclass_lds[sht::kNumRingClasses] = {};
     // the Bluestein fast path takes complex64 Delta (the mixed forms)
     const bool blue_ok = d->precision != SHT_FP64 && mval.back() < sht::kFastMaxModes;
     for (int r = 0; r < R; ++r) {
@@ -457,6 +461,8 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
         } else if (g.np > 0) {
             ring_sclass[r] = sht::kBlueClass;
             sht::blue_lds_add(sclass_lds[sht::kBlueClass], g.n, g.nb, mval.back());
+            ring_bclass[r] = c;
+            sht::ring_lds_add(bclass_lds[c], c, g.n, g.nb, need);
         } else {
             ring_sclass[r] = c;
             sht::ring_lds_add(sclass_lds[c], c, g.n, g.nb, need);
@@ -651,6 +657,12 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
         p->scls[c].count = (int)ids.size();
         p->scls[c].lds = sclass_lds[c];
         st = upload(&p->scls[c].d_ids, ids, &tb);
+    }
+    for (int c = 0; c < sht::kNumRingClasses && st == SHT_OK; ++c) {
+        const std::vector<int> ids = class_ids(ring_bclass, c);
+        p->bcls[c].count = (int)ids.size();
+        p->bcls[c].lds = bclass_lds[c];
+        st = upload(&p->bcls[c].d_ids, ids, &tb);
     }
     if (st == SHT_OK && !prep_ids.empty()) {
         int *d_ids = nullptr;

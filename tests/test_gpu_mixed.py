@@ -177,3 +177,11 @@ def test_mixed_bluestein_fast_rings(P, prec):
         for r in range(len(nphi)):
             gaps[start[r]:start[r] + nphi[r]] = False
         assert np.all(out[i, gaps] == 0.0), i
+    # the same plan's Fourier stage from a caller's complex128 Delta (the FP64
+    # size-class kernels take these rings then)
+    dls = [ref.delta(L, None, g.cth, g.sth, alms[i]) for i in range(nmaps)]
+    d_dev = torch.from_numpy(np.stack([np.ascontiguousarray(d.T) for d in dls])).to(_dev())
+    got = plan.delta2map(d_dev).cpu().numpy()
+    for i in range(nmaps):
+        em = ref.map_from_delta(np.arange(L + 1), g, dls[i])
+        assert _rel(got[i], em) < 1e-12, i
