@@ -489,7 +489,8 @@ def main() -> int:
         fb = forms[best]
         res.update({
             "value": B / t, "unit": "maps/s", "ms_per_step": t * 1e3,
-            "dtype": FORMS[best][3] + " matrix-core contraction + f64 recurrence and FFT",
+            "dtype": FORMS[best][3] + " matrix-core contraction + f64 recurrence and alias "
+                     "fold + f32 ring FFT",
             "config": {"workload": f"alm2map mixed precision, batch of {B} maps, lmax={Lmax}, "
                                    f"HEALPix nside={N}", "lmax": Lmax, "nside": N,
                        "nmaps": B, "precision": best, "npix": geom.npix,
