@@ -233,6 +233,19 @@ __device__ __attribute__((always_inline)) inline void load_tw(C *T, const double
     }
 }
 
+// The same from a complex64 copy of the table.
+template <int NT>
+__device__ __attribute__((always_inline)) inline void load_tw(float2 *T,
+                                                              const float2 *__restrict__ tab,
+                                                              int L)
+{
+    const int n1 = (L + 63) >> 6;
+    for (int e = threadIdx.x; e < 64 + n1; e += NT) {
+        const int t = (e < 64) ? e : 64 * (e - 64);
+        T[e] = (t < L) ? tab[t] : make_float2(1.0f, 0.0f);
+    }
+}
+
 template <typename C>
 __device__ inline C tw_at(const C *T, int t)
 {
@@ -1102,7 +1115,7 @@ enum BlueIn { kBlueInZ, kBlueInBuf, kBlueInBq };
 
 struct BlueRing {
     int h, len;
-    const double2 *bq;   // kernel spectrum DFT^-(conj chirp, wrapped) / nb
+    const float2 *bq;    // kernel spectrum DFT^-(conj chirp, wrapped) / nb
     double *out;         // the ring's first pixel
 };
 
@@ -1132,7 +1145,7 @@ __device__ __attribute__((always_inline)) inline void blue_pass(float2 *X, float
             const int j = tid + q * NT;
             if (j < nbf) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) a[q][r] = cvt<C>(br.bq[j + r * nbf]);
+                for (int r = 0; r < R; ++r) a[q][r] = br.bq[j + r * nbf];
             }
         }
     }
@@ -1283,7 +1296,7 @@ __device__ __attribute__((always_inline)) inline void blue_dir(float2 *X, float2
 // before the current ring's passes); complex64 Delta only.
 __global__ __launch_bounds__(kBlueThreads, 4) void k_ring_synth_blue(
     const int *__restrict__ ids, int count, int nmaps, const RingDesc *__restrict__ rings,
-    const double2 *__restrict__ pool, const float2 *__restrict__ delta,
+    const float2 *__restrict__ pool32, const float2 *__restrict__ delta,
     const int *__restrict__ minv, int mcontig, int mmax, int nm, int nrings,
     double *__restrict__ map, long long npix, RingLds lds)
 {
@@ -1310,11 +1323,11 @@ __global__ __launch_bounds__(kBlueThreads, 4) void k_ring_synth_blue(
         BlueRing br;
         br.h = d.n / 2;
         br.len = br.h / 2;
-        br.bq = pool + d.bq;
+        br.bq = pool32 + d.bq;
         br.out = map + b * npix + d.start;
         if (!first) __syncthreads();   // the previous ring's last pass has read TW
-        load_tw<kBlueThreads>(TW, pool + d.tw, d.n);
-        load_tw<kBlueThreads>(TB, pool + d.twb, d.nb);
+        load_tw<kBlueThreads>(TW, pool32 + d.tw, d.n);
+        load_tw<kBlueThreads>(TB, pool32 + d.twb, d.nb);
         fold_fast<kBlueThreads>(X, d, raw, mmax);
         const long long nx = it + per;
         if (nx < hi) {
@@ -1551,8 +1564,9 @@ hipError_t synth_blue_class(const sht_plan_s *p, const float2 *delta, double *ma
     long long grid = 2LL * (p->num_cus > 0 ? p->num_cus : 256);
     if (grid > items) grid = items;
     grid = ((grid + 7) / 8) * 8;
+    if (!p->d_pool32) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_ring_synth_blue, dim3((unsigned)grid), dim3(kBlueThreads), lds, st,
-                       rc.d_ids, rc.count, p->nmaps, p->d_rings, p->d_pool, delta, p->d_minv,
+                       rc.d_ids, rc.count, p->nmaps, p->d_rings, p->d_pool32, delta, p->d_minv,
                        p->mcontig, p->mmax, p->nm, p->nrings, map, p->npix, rc.lds);
     return hipGetLastError();
 }
@@ -1628,6 +1642,22 @@ __global__ __launch_bounds__(256) void k_widen(const float2 *__restrict__ s,
 {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i < n) d[i] = make_double2((double)s[i].x, (double)s[i].y);
+}
+
+__global__ __launch_bounds__(256) void k_narrow(const double2 *__restrict__ s,
+                                                float2 *__restrict__ d, long long n)
+{
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) d[i] = make_float2((float)s[i].x, (float)s[i].y);
+}
+
+hipError_t launch_narrow(const double2 *s, float2 *d, long long n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const long long nb = (n + 255) / 256;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_narrow, dim3((unsigned)nb), dim3(256), 0, st, s, d, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_widen(const float2 *s, double2 *d, long long n, hipStream_t st)

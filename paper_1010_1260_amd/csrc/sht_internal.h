@@ -257,6 +257,7 @@ struct sht_plan_s {
     long long nsuper;    // 128-row super-blocks over all m
     sht::RingDesc *d_rings;
     double2 *d_pool;     // twiddle and Bluestein tables
+    float2 *d_pool32;    // complex64 copy of d_pool (plans with a Bluestein fast path)
     size_t table_bytes;
     size_t pool_entries;
     int mcontig;         // m-set is 0..nm-1
@@ -318,6 +319,7 @@ hipError_t launch_ring_synth(const sht_plan_s *p, const double2 *delta, double *
 hipError_t launch_ring_synth(const sht_plan_s *p, const float2 *delta, double *map,
                              hipStream_t st);
 hipError_t launch_widen(const float2 *s, double2 *d, long long n, hipStream_t st);
+hipError_t launch_narrow(const double2 *s, float2 *d, long long n, hipStream_t st);
 hipError_t launch_ring_anal(const sht_plan_s *p, const double *map, double2 *dt, hipStream_t st,
                             const double *rw = nullptr, double cfac = 2.0);
 hipError_t launch_residual(const double *s, double *r, long long n, hipStream_t st);

@@ -169,7 +169,7 @@ void free_tables(sht_plan_s *p)
 {
     void *ptrs[] = {p->d_pairs, p->d_mval, p->d_moff, p->d_mu, p->d_A, p->d_cn,
                     p->d_minv, p->d_rings, p->d_pool, p->d_boff, p->d_boff16, p->d_bm16,
-                    p->d_bm32, p->d_soff, p->d_sbm, p->d_Asb};
+                    p->d_bm32, p->d_soff, p->d_sbm, p->d_Asb, p->d_pool32};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (int c = 0; c < sht::kNumSynthClasses; ++c) {
@@ -186,6 +186,7 @@ void free_tables(sht_plan_s *p)
     p->d_A = nullptr; p->d_cn = nullptr; p->d_minv = nullptr; p->d_rings = nullptr;
     p->d_pool = nullptr; p->d_boff = nullptr; p->d_boff16 = nullptr; p->d_bm16 = nullptr;
     p->d_bm32 = nullptr; p->d_soff = nullptr; p->d_sbm = nullptr; p->d_Asb = nullptr;
+    p->d_pool32 = nullptr;
 }
 
 sht_status check_plan(sht_plan_t p)
@@ -675,6 +676,21 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
                 hipDeviceSynchronize() != hipSuccess)
                 st = SHT_ERR_HIP;
             (void)hipFree(d_ids);
+        }
+    }
+    // the Bluestein fast path reads its tables (kernel spectra, twiddles) in
+    // complex64: 8-byte loads, no conversions in the passes
+    if (st == SHT_OK && p->scls[sht::kBlueClass].count > 0) {
+        const size_t bytes = p->pool_entries * sizeof(float2);
+        if (hipMalloc((void **)&p->d_pool32, bytes) != hipSuccess) {
+            p->d_pool32 = nullptr;
+            st = SHT_ERR_OOM;
+        } else if (sht::launch_narrow(p->d_pool, p->d_pool32, (long long)p->pool_entries,
+                                      nullptr) != hipSuccess ||
+                   hipDeviceSynchronize() != hipSuccess) {
+            st = SHT_ERR_HIP;
+        } else {
+            tb += bytes;
         }
     }
     if (st != SHT_OK) {
