@@ -253,10 +253,11 @@ sht_status sht_alm2map_noalloc(sht_plan_t plan, const double *alm, double *map, 
  * Eq. (DeltaDef) for the i-th m of the set at [b][i][r] (rings contiguous:
  * the Legendre stage writes whole runs of rings per m).
  * The mixed forms keep Delta as complex64 inside sht_alm2map (the precision
- * of their FP32 sums), and their ring FFTs on the fast paths run in
- * complex64 (the alias fold adds in FP64); sht_alm2delta of a mixed plan
- * writes that complex64 Delta into the workspace and widens it exactly into
- * `delta`, so it needs sht_plan_info.forward_workspace_bytes (FP64 plans: the
+ * of their FP32 sums), laid out [m][ring][map] (maps contiguous, read by the
+ * ring stage for all maps of a ring together), and their ring FFTs on the
+ * fast paths run in complex64 (the alias fold adds in FP64); sht_alm2delta
+ * of a mixed plan writes that complex64 Delta into the workspace and widens
+ * it exactly into `delta` in the layout above, so it needs sht_plan_info.forward_workspace_bytes (FP64 plans: the
  * coefficient part only).  sht_delta2map always reads complex128 and runs
  * the Fourier stage in FP64, on any plan. */
 sht_status sht_alm2delta(sht_plan_t plan, const double *alm, double *delta,

@@ -94,10 +94,12 @@ __device__ __forceinline__ void block16_dead_g(double x, double &ua, double &ub,
 
 // Delta of one m.  D layout of a 32x32 tile: column = lane % 32 (the ring
 // pair), row = 8 (r/4) + 4 (lane/32) + r % 4 = 2 map + Re/Im, so a lane owns
-// 8 complex values of one pair and a half-wave stores 32 consecutive rings
-// of Delta [map][m][ring].  The parity sums are FP32; north (E + O) and
-// south (E - O) are formed exactly in FP64 and rounded once to FP32, the
-// precision the contraction carries, so Delta is stored as complex64.
+// 8 complex values of one pair.  The mixed forms' Delta is [m][ring][map]
+// (maps contiguous): the ring stage reads a ring's modes for all maps at
+// once, and the wave writes every map of its rings, so each line is filled
+// by one wave.  The parity sums are FP32; north (E + O) and south (E - O)
+// are formed exactly in FP64 and rounded once to FP32, the precision the
+// contraction carries, so Delta is stored as complex64.
 __device__ __forceinline__ void m_store(const MfmaTiles &tot, int i, float2 *__restrict__ delta,
                                         const PairDesc *__restrict__ pairs, int npairs, int pb,
                                         int grp, int nmaps, int nrings, int nm, int lane)
@@ -112,16 +114,36 @@ __device__ __forceinline__ void m_store(const MfmaTiles &tot, int i, float2 *__r
         const int pp = pb * 64 + h * 32 + col;
         if (pp < npairs) {
             const PairDesc d = pairs[pp];
+            const long long row = (long long)i * nrings;
+            float2 *__restrict__ dn = d2 + (row + d.rn) * nmaps;
+            float2 *__restrict__ ds = d2 + (row + (d.rs >= 0 ? d.rs : d.rn)) * nmaps;
 #pragma unroll
-            for (int r = 0; r < 16; r += 2) {
-                const int map = grp * 16 + 4 * (r >> 2) + 2 * hi + ((r & 3) >> 1);
-                if (map < nmaps) {
-                    const double er = E[r], ei = E[r + 1], orr = O[r], oi = O[r + 1];
-                    d2[((long long)map * nm + i) * nrings + d.rn] =
-                        make_float2((float)(er + orr), (float)(ei + oi));
+            for (int r = 0; r < 16; r += 4) {
+                // rows r .. r + 3: maps m0 and m0 + 1, adjacent in Delta, so
+                // one 16-byte store takes both when the alignment allows
+                const int m0 = grp * 16 + 4 * (r >> 2) + 2 * hi;
+                float2 n[2], so[2];
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const double er = E[r + 2 * k], ei = E[r + 2 * k + 1];
+                    const double orr = O[r + 2 * k], oi = O[r + 2 * k + 1];
+                    n[k] = make_float2((float)(er + orr), (float)(ei + oi));
+                    so[k] = make_float2((float)(er - orr), (float)(ei - oi));
+                }
+                if (m0 + 1 < nmaps && (nmaps & 1) == 0) {
+                    *reinterpret_cast<float4 *>(dn + m0) =
+                        make_float4(n[0].x, n[0].y, n[1].x, n[1].y);
                     if (d.rs >= 0)
-                        d2[((long long)map * nm + i) * nrings + d.rs] =
-                            make_float2((float)(er - orr), (float)(ei - oi));
+                        *reinterpret_cast<float4 *>(ds + m0) =
+                            make_float4(so[0].x, so[0].y, so[1].x, so[1].y);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) {
+                        if (m0 + k < nmaps) {
+                            dn[m0 + k] = n[k];
+                            if (d.rs >= 0) ds[m0 + k] = so[k];
+                        }
+                    }
                 }
             }
         }

@@ -502,16 +502,62 @@ __device__ inline int xcd_logical(int b, int total)
     return x * q + (x < r ? x : r) + i;
 }
 
-// Work item -> (index in the class's ring list, map): map by map, ring by
-// ring, so that the workgroups running together read neighbouring rings of
-// one map (whose Delta entries share cache lines and DRAM pages).  Measured
-// faster than grouping a few rings' items of all maps together, which would
-// keep each ring's tables in L2 but spreads the Delta reads over all maps.
-__device__ inline void ring_item(long long it, int count, int &i, int &b)
+// Work item -> (index in the class's ring list, map), so that the
+// workgroups running together read Delta entries that share cache lines and
+// DRAM pages: for [map][m][ring] Delta map by map, ring by ring
+// (neighbouring rings of one map; measured faster than grouping a few rings'
+// items of all maps together, which would keep each ring's tables in L2 but
+// spreads the Delta reads over all maps); for [m][ring][map] Delta ring by
+// ring, map by map (all maps of one ring).
+template <bool RM>
+__device__ inline void ring_item(long long it, int count, int nmaps, int &i, int &b)
 {
-    b = (int)(it / count);
-    i = (int)(it - (long long)b * count);
+    if (RM) {
+        i = (int)(it / nmaps);
+        b = (int)(it - (long long)i * nmaps);
+    } else {
+        b = (int)(it / count);
+        i = (int)(it - (long long)b * count);
+    }
 }
+
+// The persistent kernels' share of XCD x (workgroups are dealt to the 8 XCDs
+// round-robin): items [lo, hi) of its own numbering, item k -> (i, b).  Map
+// by map: a contiguous eighth of all items.  Ring by ring: the rings
+// i = x mod 8 (the class's rings are sorted by length, so every XCD gets
+// rings of every length), all maps of a ring together.
+template <bool RM>
+__device__ inline void xcd_share(int count, int nmaps, int x, long long &lo, long long &hi)
+{
+    if (RM) {
+        lo = 0;
+        hi = (long long)((count - x + 7) / 8) * nmaps;
+    } else {
+        const long long total = (long long)count * nmaps;
+        lo = total * x / 8;
+        hi = total * (x + 1) / 8;
+    }
+}
+
+template <bool RM>
+__device__ inline void xcd_item(long long k, int count, int nmaps, int x, int &i, int &b)
+{
+    if (RM) {
+        const long long q = k / nmaps;
+        i = (int)(x + 8 * q);
+        b = (int)(k - q * nmaps);
+    } else {
+        ring_item<false>(k, count, nmaps, i, b);
+    }
+}
+
+// complex64 Delta (the mixed forms') is [m][ring][map], its items ring by ring
+template <typename DT> struct RingMajor {
+    static constexpr bool value = false;
+};
+template <> struct RingMajor<float2> {
+    static constexpr bool value = true;
+};
 
 // Delta_m for mode m of a ring (zero for m outside the set); Delta is laid
 // out [m][ring], so the ring's modes are `dstride` entries apart.  DT is the
@@ -1044,25 +1090,25 @@ template <typename DT>
 __global__ __launch_bounds__(kFastThreads, FastPrec<DT>::kBlocks) void k_ring_synth_fast(
     const int *__restrict__ ids, int count, int nmaps, const RingDesc *__restrict__ rings,
     const double2 *__restrict__ pool, const DT *__restrict__ delta,
-    const int *__restrict__ minv, int mcontig, int mmax, int nm, int nrings,
+    const int *__restrict__ minv, int mcontig, int mmax, DeltaLayout dl,
     double *__restrict__ map, long long npix, RingLds lds)
 {
     typedef typename FastPrec<DT>::C C;
     extern __shared__ double2 lds_raw[];
     C *buf = reinterpret_cast<C *>(lds_raw);
     C *T = buf + lds.fft_entries;
-    const long long total = (long long)count * nmaps;
     const int per = (int)(gridDim.x / 8);
     const int x = (int)(blockIdx.x % 8), w = (int)(blockIdx.x / 8);
-    const long long hi = total * (x + 1) / 8;
-    long long it = total * x / 8 + w;
+    long long lo, hi;
+    xcd_share<RingMajor<DT>::value>(count, nmaps, x, lo, hi);
+    long long it = lo + w;
     if (it >= hi) return;
     int i, bi;
-    ring_item(it, count, i, bi);
+    xcd_item<RingMajor<DT>::value>(it, count, nmaps, x, i, bi);
     long long b = bi;
     int r = ids[i];
     FastModes<kFastThreads, DT> raw;
-    load_fast<kFastThreads>(raw, delta + b * nm * nrings + r, nrings, minv, mcontig, mmax);
+    load_fast<kFastThreads>(raw, delta + b * dl.map + r * dl.ring, dl.m, minv, mcontig, mmax);
     for (bool first = true;; first = false) {
         const RingDesc d = rings[r];
         double *out = map + b * npix + d.start;
@@ -1071,10 +1117,10 @@ __global__ __launch_bounds__(kFastThreads, FastPrec<DT>::kBlocks) void k_ring_sy
         fold_fast<kFastThreads>(buf, d, raw, mmax);
         const long long nx = it + per;
         if (nx < hi) {
-            ring_item(nx, count, i, bi);
+            xcd_item<RingMajor<DT>::value>(nx, count, nmaps, x, i, bi);
             b = bi;
             r = ids[i];
-            load_fast<kFastThreads>(raw, delta + b * nm * nrings + r, nrings, minv, mcontig, mmax);
+            load_fast<kFastThreads>(raw, delta + b * dl.map + r * dl.ring, dl.m, minv, mcontig, mmax);
         }
         fft_fast<kFastThreads, C>(buf, T, d, out);
         if (nx >= hi) break;
@@ -1297,7 +1343,7 @@ __device__ __attribute__((always_inline)) inline void blue_dir(float2 *X, float2
 __global__ __launch_bounds__(kBlueThreads, 4) void k_ring_synth_blue(
     const int *__restrict__ ids, int count, int nmaps, const RingDesc *__restrict__ rings,
     const float2 *__restrict__ pool32, const float2 *__restrict__ delta,
-    const int *__restrict__ minv, int mcontig, int mmax, int nm, int nrings,
+    const int *__restrict__ minv, int mcontig, int mmax, DeltaLayout dl,
     double *__restrict__ map, long long npix, RingLds lds)
 {
     typedef float2 C;
@@ -1306,18 +1352,18 @@ __global__ __launch_bounds__(kBlueThreads, 4) void k_ring_synth_blue(
     C *Y = X + lds.fft_entries;
     C *TW = Y + lds.y_entries;
     C *TB = TW + lds.tw_entries;
-    const long long total = (long long)count * nmaps;
     const int per = (int)(gridDim.x / 8);
     const int x = (int)(blockIdx.x % 8), w = (int)(blockIdx.x / 8);
-    const long long hi = total * (x + 1) / 8;
-    long long it = total * x / 8 + w;
+    long long lo, hi;
+    xcd_share<true>(count, nmaps, x, lo, hi);
+    long long it = lo + w;
     if (it >= hi) return;
     int i, bi;
-    ring_item(it, count, i, bi);
+    xcd_item<true>(it, count, nmaps, x, i, bi);
     long long b = bi;
     int r = ids[i];
     FastModes<kBlueThreads, float2> raw;
-    load_fast<kBlueThreads>(raw, delta + b * nm * nrings + r, nrings, minv, mcontig, mmax);
+    load_fast<kBlueThreads>(raw, delta + b * dl.map + r * dl.ring, dl.m, minv, mcontig, mmax);
     for (bool first = true;; first = false) {
         const RingDesc d = rings[r];
         BlueRing br;
@@ -1331,10 +1377,10 @@ __global__ __launch_bounds__(kBlueThreads, 4) void k_ring_synth_blue(
         fold_fast<kBlueThreads>(X, d, raw, mmax);
         const long long nx = it + per;
         if (nx < hi) {
-            ring_item(nx, count, i, bi);
+            xcd_item<true>(nx, count, nmaps, x, i, bi);
             b = bi;
             r = ids[i];
-            load_fast<kBlueThreads>(raw, delta + b * nm * nrings + r, nrings, minv, mcontig,
+            load_fast<kBlueThreads>(raw, delta + b * dl.map + r * dl.ring, dl.m, minv, mcontig,
                                     mmax);
         }
         blue_dir<-1>(X, Y, TW, TB, d, br);
@@ -1348,19 +1394,19 @@ template <int NT, int MAXN, typename DT>
 __global__ __launch_bounds__(NT, 4) void k_ring_synth(
     const int *__restrict__ ids, int count, int nmaps, const RingDesc *__restrict__ rings,
     const double2 *__restrict__ pool, const DT *__restrict__ delta,
-    const int *__restrict__ minv, int mcontig, int mmax, int nm, int nrings,
+    const int *__restrict__ minv, int mcontig, int mmax, DeltaLayout dl,
     double *__restrict__ map, long long npix, RingLds lds)
 {
     extern __shared__ double2 buf[];
     int i, bi;
-    ring_item(xcd_logical(blockIdx.x, gridDim.x), count, i, bi);
+    ring_item<RingMajor<DT>::value>(xcd_logical(blockIdx.x, gridDim.x), count, nmaps, i, bi);
     const int r = ids[i];
     const long long b = bi;
     const RingDesc d = rings[r];
     double2 *tw = buf + lds.fft_entries;
     const RingTables rt = {tw, tw + lds.tw_entries};
     synth_ring<NT, MAXN, false, false>(buf, rt, d,
-                               pool, delta + b * nm * nrings + r, nrings, minv,
+                               pool, delta + b * dl.map + r * dl.ring, dl.m, minv,
                                mcontig, mmax, map + b * npix + d.start);
 }
 
@@ -1489,6 +1535,18 @@ __global__ __launch_bounds__(512) void k_bluestein_prep(
         pool[d.bq + k] = make_double2(buf[k].x * inv, buf[k].y * inv);
 }
 
+// The layout of the ring stage's Delta by its element type: complex64 is the
+// mixed Legendre stage's [m][ring][map], complex128 the FP64 stage's (or a
+// caller's) [map][m][ring].
+DeltaLayout delta_layout(const sht_plan_s *p, const float2 *)
+{
+    return DeltaLayout{1, p->nmaps, (long long)p->nrings * p->nmaps};
+}
+DeltaLayout delta_layout(const sht_plan_s *p, const double2 *)
+{
+    return DeltaLayout{(long long)p->nm * p->nrings, 1, p->nrings};
+}
+
 hipError_t set_lds(const void *fn, size_t bytes)
 {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -1506,7 +1564,7 @@ hipError_t synth_class(const sht_plan_s *p, const RingClass &rc, const DT *delta
     if (items > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((k_ring_synth<NT, MAXN, DT>), dim3((unsigned)items), dim3(NT), lds, st,
                        rc.d_ids, rc.count, p->nmaps, p->d_rings, p->d_pool, delta, p->d_minv,
-                       p->mcontig, p->mmax, p->nm, p->nrings, map, p->npix, rc.lds);
+                       p->mcontig, p->mmax, delta_layout(p, delta), map, p->npix, rc.lds);
     return hipGetLastError();
 }
 
@@ -1546,7 +1604,8 @@ hipError_t synth_fast_class(const sht_plan_s *p, const DT *delta, double *map, h
     grid = ((grid + 7) / 8) * 8;
     hipLaunchKernelGGL((k_ring_synth_fast<DT>), dim3((unsigned)grid), dim3(kFastThreads), lds,
                        st, rc.d_ids, rc.count, p->nmaps, p->d_rings, p->d_pool, delta,
-                       p->d_minv, p->mcontig, p->mmax, p->nm, p->nrings, map, p->npix, rc.lds);
+                       p->d_minv, p->mcontig, p->mmax, delta_layout(p, delta), map, p->npix,
+                       rc.lds);
     return hipGetLastError();
 }
 
@@ -1567,7 +1626,7 @@ hipError_t synth_blue_class(const sht_plan_s *p, const float2 *delta, double *ma
     if (!p->d_pool32) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_ring_synth_blue, dim3((unsigned)grid), dim3(kBlueThreads), lds, st,
                        rc.d_ids, rc.count, p->nmaps, p->d_rings, p->d_pool32, delta, p->d_minv,
-                       p->mcontig, p->mmax, p->nm, p->nrings, map, p->npix, rc.lds);
+                       p->mcontig, p->mmax, delta_layout(p, delta), map, p->npix, rc.lds);
     return hipGetLastError();
 }
 
@@ -1637,13 +1696,6 @@ hipError_t launch_ring_synth(const sht_plan_s *p, const float2 *delta, double *m
 }
 
 // Complex64 Delta widened to complex128 (the stage entry point's layout).
-__global__ __launch_bounds__(256) void k_widen(const float2 *__restrict__ s,
-                                               double2 *__restrict__ d, long long n)
-{
-    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) d[i] = make_double2((double)s[i].x, (double)s[i].y);
-}
-
 __global__ __launch_bounds__(256) void k_narrow(const double2 *__restrict__ s,
                                                 float2 *__restrict__ d, long long n)
 {
@@ -1660,12 +1712,30 @@ hipError_t launch_narrow(const double2 *s, float2 *d, long long n, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_widen(const float2 *s, double2 *d, long long n, hipStream_t st)
+// complex64 [m][ring][map] Delta of the mixed forms -> complex128
+// [map][m][ring] (exact), one thread per output entry.
+__global__ __launch_bounds__(256) void k_widen_delta(const float2 *__restrict__ s,
+                                                     double2 *__restrict__ d, int nmaps, int nm,
+                                                     int nrings)
 {
+    const long long n = (long long)nmaps * nm * nrings;
+    const long long o = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (o >= n) return;
+    const long long per_map = (long long)nm * nrings;
+    const int b = (int)(o / per_map);
+    const long long rem = o - b * per_map;   // i * nrings + r
+    const float2 v = s[rem * nmaps + b];
+    d[o] = make_double2((double)v.x, (double)v.y);
+}
+
+hipError_t launch_widen_delta(const sht_plan_s *p, const float2 *s, double2 *d, hipStream_t st)
+{
+    const long long n = (long long)p->nmaps * p->nm * p->nrings;
     if (n <= 0) return hipSuccess;
     const long long nb = (n + 255) / 256;
     if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_widen, dim3((unsigned)nb), dim3(256), 0, st, s, d, n);
+    hipLaunchKernelGGL(k_widen_delta, dim3((unsigned)nb), dim3(256), 0, st, s, d, p->nmaps, p->nm,
+                       p->nrings);
     return hipGetLastError();
 }
 

@@ -52,6 +52,18 @@ struct PairDesc {
 
 // Rings grouped by FFT length for the Fourier kernels (LDS and register
 // budgets differ per class): class 0 up to 2048 points, 1 up to 4096, 2 up to 8192.
+// Element strides of a Delta buffer, and the order of the ring stage's
+// (map, ring) items.  complex128 Delta (the FP64 Legendre stage's, or a
+// caller's) is [map][m][ring]: neighbouring rings of one map share cache
+// lines, so the items run map by map.  The mixed forms' complex64 Delta is
+// [m][ring][map]: the maps of one ring share lines, so the items run ring by
+// ring.
+struct DeltaLayout {
+    long long map;    // stride between maps
+    long long ring;   // between rings
+    long long m;      // between the modes of one (map, ring)
+};
+
 // LDS of a ring-class workgroup, in complex entries: the spectrum / FFT
 // buffer (which also stages partial alias sums during the fold), the second
 // convolution buffer of the Bluestein fast path (y, 0 elsewhere), and the
@@ -318,7 +330,8 @@ hipError_t launch_ring_synth(const sht_plan_s *p, const double2 *delta, double *
                              hipStream_t st);
 hipError_t launch_ring_synth(const sht_plan_s *p, const float2 *delta, double *map,
                              hipStream_t st);
-hipError_t launch_widen(const float2 *s, double2 *d, long long n, hipStream_t st);
+// the mixed forms' complex64 [m][ring][map] Delta -> complex128 [map][m][ring]
+hipError_t launch_widen_delta(const sht_plan_s *p, const float2 *s, double2 *d, hipStream_t st);
 hipError_t launch_narrow(const double2 *s, float2 *d, long long n, hipStream_t st);
 hipError_t launch_ring_anal(const sht_plan_s *p, const double *map, double2 *dt, hipStream_t st,
                             const double *rw = nullptr, double cfac = 2.0);

@@ -829,9 +829,7 @@ sht_status sht_alm2delta(sht_plan_t p, const double *alm, double *delta, void *w
     float2 *d32 = (float2 *)((char *)ws + p->ws_ap_bytes);
     s = legendre_stage(p, alm, ws, d32, (hipStream_t)stream, nullptr);
     if (s == SHT_OK)
-        s = from_hip(sht::launch_widen(d32, (double2 *)delta,
-                                       (long long)p->nmaps * p->nm * p->nrings,
-                                       (hipStream_t)stream));
+        s = from_hip(sht::launch_widen_delta(p, d32, (double2 *)delta, (hipStream_t)stream));
     return s;
 }
 
