@@ -1161,9 +1161,22 @@ enum BlueIn { kBlueInZ, kBlueInBuf, kBlueInBq };
 
 struct BlueRing {
     int h, len;
+    float inv_h;         // 1 / h, rounded
     const float2 *bq;    // kernel spectrum DFT^-(conj chirp, wrapped) / nb
     double *out;         // the ring's first pixel
 };
+
+// k^2 mod h for k < 2^11 and h < 2^13, exactly: k^2 < 2^22 is exact in
+// FP32, and the rounded quotient k^2 * (1/h) is within 0.05 of k^2 / h, so
+// one correction either way restores the remainder.
+__device__ inline int sq_mod(int k, int h, float inv_h)
+{
+    const int k2 = k * k;
+    const int q = (int)((float)k2 * inv_h);
+    int r = k2 - q * h;
+    r = (r < 0) ? r + h : r;
+    return (r >= h) ? r - h : r;
+}
 
 // One pass of radix R over both nb-point buffers (input index j + r nb/R,
 // output index (j / Ns) Ns R + j % Ns + r Ns); TB holds the nb-th roots,
@@ -1215,8 +1228,7 @@ __device__ __attribute__((always_inline)) inline void blue_pass(float2 *X, float
                                           muli(cmul(tw_at(TW, t0), csub(F0, conjd(G0))), +1));
                         const C z1 = cadd(cadd(F1, conjd(G1)),
                                           muli(cmul(tw_at(TW, t1), csub(F1, conjd(G1))), +1));
-                        const int e = (int)(((unsigned)k * (unsigned)k) % (unsigned)h);
-                        const C c = tw_at(TW, 2 * e);
+                        const C c = tw_at(TW, 2 * sq_mod(k, h, br.inv_h));
                         ae = cmul(z0, c);
                         ao = cmul(z1, c);
                     }
@@ -1272,8 +1284,7 @@ __device__ __attribute__((always_inline)) inline void blue_pass(float2 *X, float
                 for (int r = 0; r < R; ++r) {
                     const int o = j + r * nbf;
                     if (o < len) {
-                        const int e = (int)(((unsigned)o * (unsigned)o) % (unsigned)h);
-                        const C c = tw_at(TW, 2 * e);
+                        const C c = tw_at(TW, 2 * sq_mod(o, h, br.inv_h));
                         const C E = cmul(a[q][r], c);
                         const C t = cmul(tw_at(TW, 2 * o), cmul(b[q][r], c));
                         const double2 z0 = todbl(cadd(E, t)), z1 = todbl(csub(E, t));
@@ -1369,6 +1380,7 @@ __global__ __launch_bounds__(kBlueThreads, 4) void k_ring_synth_blue(
         BlueRing br;
         br.h = d.n / 2;
         br.len = br.h / 2;
+        br.inv_h = 1.0f / (float)br.h;
         br.bq = pool32 + d.bq;
         br.out = map + b * npix + d.start;
         if (!first) __syncthreads();   // the previous ring's last pass has read TW

@@ -117,9 +117,11 @@ def test_delta_deep_rescaling(P):
 
 # ------------------------------------------------------------------ Fourier
 
-@pytest.mark.parametrize("nphi", [1, 2, 3, 4, 5, 6, 7, 8, 11, 12, 13, 16, 30, 31, 64, 97, 100,
-                                  128, 210, 254, 255, 256, 1000, 1024, 2046, 4094, 4096, 8190,
-                                  8192])
+# 44, 52, 356, 8156: HEALPix polar-cap lengths 4 p with p prime (half-split
+# Bluestein)
+@pytest.mark.parametrize("nphi", [1, 2, 3, 4, 5, 6, 7, 8, 11, 12, 13, 16, 30, 31, 44, 52, 64, 97,
+                                  100, 128, 210, 254, 255, 256, 356, 1000, 1024, 2046, 4094,
+                                  4096, 8156, 8190, 8192])
 def test_ring_synthesis_parity(P, nphi):
     _say("ring synthesis nphi", nphi)
     rng = np.random.default_rng(nphi)
@@ -137,7 +139,8 @@ def test_ring_synthesis_parity(P, nphi):
     assert np.max(np.abs(got - exp)) < 1e-13 * np.max(np.abs(exp)) * max(1, np.log2(nphi + 1))
 
 
-@pytest.mark.parametrize("nphi", [1, 2, 3, 6, 7, 12, 31, 100, 254, 1000, 4094, 4096])
+@pytest.mark.parametrize("nphi", [1, 2, 3, 6, 7, 12, 31, 44, 52, 100, 254, 356, 1000, 4094,
+                                  4096, 8156])
 def test_ring_analysis_parity(P, nphi):
     _say("ring analysis nphi", nphi)
     rng = np.random.default_rng(1000 + nphi)
