@@ -185,3 +185,20 @@ def test_mixed_bluestein_fast_rings(P, prec):
     for i in range(nmaps):
         em = ref.map_from_delta(np.arange(L + 1), g, dls[i])
         assert _rel(got[i], em) < 1e-12, i
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixed_gappy_mset_fast_paths(P, prec):
+    """A gappy m-set (the fold looks each mode's position up) on HEALPix
+    rings, so that both ring fast paths (smooth belt and caps, and the
+    Bluestein caps of 4 i pixels with i not 7-smooth) take it, against the
+    oracle."""
+    _say("mixed gappy m-set on the ring fast paths", prec)
+    lmax, nside, nmaps = 300, 64, 3
+    mval = np.array([0, 1, 2, 5, 17, 40, 41, 100, 150, 199, 200, 263, 299, 300], np.int32)
+    g = W.healpix_geometry(nside)
+    alms = np.stack([W.random_alm(lmax, [307, i], mval=mval) for i in range(nmaps)])
+    plan = P.Plan(lmax, g, mval=mval, nmaps=nmaps, precision=prec)
+    got = plan.alm2map(torch.from_numpy(alms).to(_dev())).cpu().numpy()
+    for i in range(nmaps):
+        assert _rel(got[i], ref.alm2map(lmax, g, alms[i], mval=mval)) < TOL, i
