@@ -678,9 +678,10 @@ sht_status sht_plan(sht_plan_t *out, const sht_geometry_desc *d)
             (void)hipFree(d_ids);
         }
     }
-    // the Bluestein fast path reads its tables (kernel spectra, twiddles) in
-    // complex64: 8-byte loads, no conversions in the passes
-    if (st == SHT_OK && p->scls[sht::kBlueClass].count > 0) {
+    // the mixed forms' fast paths read their tables (twiddles, kernel
+    // spectra) in complex64: 8-byte loads, no conversions in the passes
+    if (st == SHT_OK && delta_f32(p) &&
+        p->scls[sht::kBlueClass].count + p->scls[sht::kFastClass].count > 0) {
         const size_t bytes = p->pool_entries * sizeof(float2);
         if (hipMalloc((void **)&p->d_pool32, bytes) != hipSuccess) {
             p->d_pool32 = nullptr;
