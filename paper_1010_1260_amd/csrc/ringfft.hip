@@ -1074,17 +1074,18 @@ __device__ __attribute__((always_inline)) inline void fft_fast(C *buf, const C *
 // buffers, and every Stockham pass takes its butterflies in both with the
 // same twiddles and one barrier pair.  `two` is false for the last map of an
 // odd map count (its partner's loads read zeros and its stores are skipped).
+template <int NT>
 struct FastModes2 {
-    static constexpr int Q = FastModes<kFastThreads, float2>::Q;
+    static constexpr int Q = FastModes<NT, float2>::Q;
     float4 v[Q];   // (map 2p, map 2p + 1) of mode tid + q NT
 };
 
+template <int NT>
 __device__ __attribute__((always_inline)) inline void load_fast2(
-    FastModes2 &raw, const float2 *__restrict__ drow, long long dstride,
+    FastModes2<NT> &raw, const float2 *__restrict__ drow, long long dstride,
     const int *__restrict__ minv, int mcontig, int mmax, bool aligned, bool two)
 {
-    constexpr int QM = FastModes2::Q;
-    constexpr int NT = kFastThreads;
+    constexpr int QM = FastModes2<NT>::Q;
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     // paced like load_fast: each load waits for the one before it
@@ -1118,13 +1119,13 @@ __device__ __attribute__((always_inline)) inline void load_fast2(
 }
 
 // fold_fast for both maps (same order of additions per map).
+template <int NT>
 __device__ __attribute__((always_inline)) inline void fold_fast2(float2 *X0, float2 *X1,
                                                                  const RingDesc &d,
-                                                                 const FastModes2 &raw,
+                                                                 const FastModes2<NT> &raw,
                                                                  int mmax)
 {
-    constexpr int QM = FastModes2::Q;
-    constexpr int NT = kFastThreads;
+    constexpr int QM = FastModes2<NT>::Q;
     const int tid = threadIdx.x;
     double2 ph, step;
     {
@@ -1375,8 +1376,9 @@ __global__ __launch_bounds__(kFastThreads, 2) void k_ring_synth_fast2(
     int r = ids[i];
     long long b = 2LL * pi;
     bool two = b + 1 < nmaps;
-    FastModes2 raw;
-    load_fast2(raw, delta + b * dl.map + r * dl.ring, dl.m, minv, mcontig, mmax, aligned, two);
+    FastModes2<kFastThreads> raw;
+    load_fast2<kFastThreads>(raw, delta + b * dl.map + r * dl.ring, dl.m, minv, mcontig, mmax,
+                             aligned, two);
     for (bool first = true;; first = false) {
         const RingDesc d = rings[r];
         double *out0 = map + b * npix + d.start;
@@ -1384,15 +1386,15 @@ __global__ __launch_bounds__(kFastThreads, 2) void k_ring_synth_fast2(
         const bool two_now = two;
         if (!first) __syncthreads();   // the previous ring's last pass has read X0, X1, T
         load_tw<kFastThreads>(T, pool32 + d.tw, d.n);
-        fold_fast2(X0, X1, d, raw, mmax);
+        fold_fast2<kFastThreads>(X0, X1, d, raw, mmax);
         const long long nx = it + per;
         if (nx < hi) {
             xcd_item<true>(nx, count, npairs, x, i, pi);
             r = ids[i];
             b = 2LL * pi;
             two = b + 1 < nmaps;
-            load_fast2(raw, delta + b * dl.map + r * dl.ring, dl.m, minv, mcontig, mmax, aligned,
-                       two);
+            load_fast2<kFastThreads>(raw, delta + b * dl.map + r * dl.ring, dl.m, minv, mcontig,
+                                     mmax, aligned, two);
         }
         fft_fast2(X0, X1, T, d, out0, out1, two_now);
         if (nx >= hi) break;
@@ -1496,7 +1498,6 @@ struct BlueRing {
     int h, len;
     float inv_h;         // 1 / h, rounded
     const float2 *bq;    // kernel spectrum DFT^-(conj chirp, wrapped) / nb
-    double *out;         // the ring's first pixel
 };
 
 // k^2 mod h for k < 2^11 and h < 2^13, exactly: k^2 < 2^22 is exact in
@@ -1511,124 +1512,132 @@ __device__ inline int sq_mod(int k, int h, float inv_h)
     return (r >= h) ? r - h : r;
 }
 
-// One pass of radix R over both nb-point buffers (input index j + r nb/R,
-// output index (j / Ns) Ns R + j % Ns + r Ns); TB holds the nb-th roots,
-// TW the n-th roots.  last: Ns R = nb, the pass ends in the pixel stores.
-template <int R, int sign>
-__device__ __attribute__((always_inline)) inline void blue_pass(float2 *X, float2 *Y,
-                                                                const float2 *TW,
-                                                                const float2 *TB, int L,
-                                                                int Ns, int in, bool last,
-                                                                const BlueRing &br)
+// One pass of radix R over both nb-point buffers of each of NM maps (input
+// index j + r nb/R, output index (j / Ns) Ns R + j % Ns + r Ns); TB holds the
+// nb-th roots, TW the n-th roots; the maps share every twiddle.  last:
+// Ns R = nb, the pass ends in the pixel stores (of the first nout maps).
+// The kernel runs one map per workgroup: two maps (four buffers) fit one
+// workgroup per CU and measured slower (caps of 16 maps at nside 2048:
+// 4.01 against 3.75 ms), unlike the fast path's two-map kernel.
+template <int R, int sign, int NM>
+__device__ __attribute__((always_inline)) inline void blue_pass(
+    float2 *const (&X)[NM], float2 *const (&Y)[NM], const float2 *TW, const float2 *TB, int L,
+    int Ns, int in, bool last, const BlueRing &br, double *const (&out)[NM], int nout)
 {
     typedef float2 C;
     constexpr int NT = kBlueThreads;
-    constexpr int MAXQ = 1;   // the plan admits nb / R <= NT
-    const int nbf = L / R;
+    const int nbf = L / R;   // the plan admits nb / R <= NT: one butterfly per thread
     const int tstep0 = L / (Ns * R);
     const unsigned magic = (unsigned)((0x100000000ull + (unsigned)Ns - 1) / (unsigned)Ns);
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    C a[MAXQ][R], b[MAXQ][R];
-    if (in == kBlueInBq) {
-        // the kernel spectrum's global loads go out before the LDS reads
+    const int j = tid;
+    C a[NM][R], b[NM][R];
+    if (j < nbf) {
+        if (in == kBlueInZ) {
+            const int h = br.h;
 #pragma unroll
-        for (int q = 0; q < MAXQ; ++q) {
-            const int j = tid + q * NT;
-            if (j < nbf) {
+            for (int r = 0; r < R; ++r) {
+                const int k = j + r * nbf;
+                if (k < br.len) {
+                    // Z_t = (F_t + conj F_{h-t}) + i e^{2 pi i t/n} (F_t - conj F_{h-t}),
+                    // t = 2k and 2k + 1
+                    const int t0 = 2 * k, t1 = t0 + 1;
+                    const C w0 = tw_at(TW, t0), w1 = tw_at(TW, t1);
+                    const C c = tw_at(TW, 2 * sq_mod(k, h, br.inv_h));
 #pragma unroll
-                for (int r = 0; r < R; ++r) a[q][r] = br.bq[j + r * nbf];
+                    for (int mm = 0; mm < NM; ++mm) {
+                        const C F0 = X[mm][PadIdx::at(t0)], G0 = X[mm][PadIdx::at(h - t0)];
+                        const C F1 = X[mm][PadIdx::at(t1)], G1 = X[mm][PadIdx::at(h - t1)];
+                        const C z0 = cadd(cadd(F0, conjd(G0)), muli(cmul(w0, csub(F0, conjd(G0))), +1));
+                        const C z1 = cadd(cadd(F1, conjd(G1)), muli(cmul(w1, csub(F1, conjd(G1))), +1));
+                        a[mm][r] = cmul(z0, c);
+                        b[mm][r] = cmul(z1, c);
+                    }
+                } else {
+#pragma unroll
+                    for (int mm = 0; mm < NM; ++mm) {
+                        a[mm][r] = make_float2(0.f, 0.f);
+                        b[mm][r] = make_float2(0.f, 0.f);
+                    }
+                }
+            }
+        } else if (in == kBlueInBq) {
+            // the kernel spectrum's global loads go out before the LDS reads
+            C wq[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) wq[r] = br.bq[j + r * nbf];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int k = PadIdx::at(j + r * nbf);
+#pragma unroll
+                for (int mm = 0; mm < NM; ++mm) {
+                    a[mm][r] = cmul(X[mm][k], wq[r]);
+                    b[mm][r] = cmul(Y[mm][k], wq[r]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int k = PadIdx::at(j + r * nbf);
+#pragma unroll
+                for (int mm = 0; mm < NM; ++mm) {
+                    a[mm][r] = X[mm][k];
+                    b[mm][r] = Y[mm][k];
+                }
             }
         }
-    }
+        if (Ns > 1) {
+            const int jq = (int)__umulhi((unsigned)j, magic);
+            const int ts = tstep0 * (j - jq * Ns);
+            if (ts != 0) {
+                C w1 = tw_at(TB, ts);
+                if (sign < 0) w1.y = -w1.y;
+                C wr = w1;
 #pragma unroll
-    for (int q = 0; q < MAXQ; ++q) {
-        const int j = tid + q * NT;
-        if (j < nbf) {
-            if (in == kBlueInZ) {
-                const int h = br.h;
+                for (int r = 1; r < R; ++r) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int k = j + r * nbf;
-                    C ae = cplx<C>(0.0, 0.0), ao = ae;
-                    if (k < br.len) {
-                        // Z_t = (F_t + conj F_{h-t}) + i e^{2 pi i t/n} (F_t - conj F_{h-t}),
-                        // t = 2k and 2k + 1
-                        const int t0 = 2 * k, t1 = t0 + 1;
-                        const C F0 = X[PadIdx::at(t0)], G0 = X[PadIdx::at(h - t0)];
-                        const C F1 = X[PadIdx::at(t1)], G1 = X[PadIdx::at(h - t1)];
-                        const C z0 = cadd(cadd(F0, conjd(G0)),
-                                          muli(cmul(tw_at(TW, t0), csub(F0, conjd(G0))), +1));
-                        const C z1 = cadd(cadd(F1, conjd(G1)),
-                                          muli(cmul(tw_at(TW, t1), csub(F1, conjd(G1))), +1));
-                        const C c = tw_at(TW, 2 * sq_mod(k, h, br.inv_h));
-                        ae = cmul(z0, c);
-                        ao = cmul(z1, c);
+                    for (int mm = 0; mm < NM; ++mm) {
+                        a[mm][r] = cmul(a[mm][r], wr);
+                        b[mm][r] = cmul(b[mm][r], wr);
                     }
-                    a[q][r] = ae;
-                    b[q][r] = ao;
-                }
-            } else if (in == kBlueInBq) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int k = PadIdx::at(j + r * nbf);
-                    const C w = a[q][r];
-                    a[q][r] = cmul(X[k], w);
-                    b[q][r] = cmul(Y[k], w);
-                }
-            } else {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int k = PadIdx::at(j + r * nbf);
-                    a[q][r] = X[k];
-                    b[q][r] = Y[k];
+                    wr = cmul(wr, w1);
                 }
             }
-            if (Ns > 1) {
-                const int jq = (int)__umulhi((unsigned)j, magic);
-                const int ts = tstep0 * (j - jq * Ns);
-                if (ts != 0) {
-                    C w1 = tw_at(TB, ts);
-                    if (sign < 0) w1.y = -w1.y;
-                    C wr = w1;
+        }
 #pragma unroll
-                    for (int r = 1; r < R; ++r) {
-                        a[q][r] = cmul(a[q][r], wr);
-                        b[q][r] = cmul(b[q][r], wr);
-                        wr = cmul(wr, w1);
-                    }
-                }
-            }
-            small_dft<R, C>(a[q], sign);
-            small_dft<R, C>(b[q], sign);
+        for (int mm = 0; mm < NM; ++mm) {
+            small_dft<R, C>(a[mm], sign);
+            small_dft<R, C>(b[mm], sign);
         }
     }
     if (last) {
         // j < Ns: outputs o = j + r nbf; for o < len, E_o = c_o a, O_o = c_o b
         const int h = br.h, len = br.len;
-        double *out = br.out;
-        const bool al = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
-        double2 *o2 = reinterpret_cast<double2 *>(out);
+        if (j < nbf) {
 #pragma unroll
-        for (int q = 0; q < MAXQ; ++q) {
-            const int j = tid + q * NT;
-            if (j < nbf) {
+            for (int r = 0; r < R; ++r) {
+                const int o = j + r * nbf;
+                if (o < len) {
+                    const C c = tw_at(TW, 2 * sq_mod(o, h, br.inv_h));
+                    const C w = tw_at(TW, 2 * o);
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int o = j + r * nbf;
-                    if (o < len) {
-                        const C c = tw_at(TW, 2 * sq_mod(o, h, br.inv_h));
-                        const C E = cmul(a[q][r], c);
-                        const C t = cmul(tw_at(TW, 2 * o), cmul(b[q][r], c));
-                        const double2 z0 = todbl(cadd(E, t)), z1 = todbl(csub(E, t));
-                        if (al) {
-                            o2[o] = z0;
-                            o2[o + len] = z1;
-                        } else {
-                            out[2 * o] = z0.x;
-                            out[2 * o + 1] = z0.y;
-                            out[2 * (o + len)] = z1.x;
-                            out[2 * (o + len) + 1] = z1.y;
+                    for (int mm = 0; mm < NM; ++mm) {
+                        if (mm < nout) {
+                            const C E = cmul(a[mm][r], c);
+                            const C t = cmul(w, cmul(b[mm][r], c));
+                            const double2 z0 = todbl(cadd(E, t)), z1 = todbl(csub(E, t));
+                            double *op = out[mm];
+                            if ((reinterpret_cast<uintptr_t>(op) & 15) == 0) {
+                                double2 *o2 = reinterpret_cast<double2 *>(op);
+                                o2[o] = z0;
+                                o2[o + len] = z1;
+                            } else {
+                                op[2 * o] = z0.x;
+                                op[2 * o + 1] = z0.y;
+                                op[2 * (o + len)] = z1.x;
+                                op[2 * (o + len) + 1] = z1.y;
+                            }
                         }
                     }
                 }
@@ -1636,17 +1645,16 @@ __device__ __attribute__((always_inline)) inline void blue_pass(float2 *X, float
         }
     } else {
         __syncthreads();
+        if (j < nbf) {
+            const int jq = (Ns == 1) ? j : (int)__umulhi((unsigned)j, magic);
+            const int base = jq * Ns * R + (j - jq * Ns);
 #pragma unroll
-        for (int q = 0; q < MAXQ; ++q) {
-            const int j = tid + q * NT;
-            if (j < nbf) {
-                const int jq = (Ns == 1) ? j : (int)__umulhi((unsigned)j, magic);
-                const int base = jq * Ns * R + (j - jq * Ns);
+            for (int r = 0; r < R; ++r) {
+                const int k = PadIdx::at(base + r * Ns);
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int k = PadIdx::at(base + r * Ns);
-                    X[k] = a[q][r];
-                    Y[k] = b[q][r];
+                for (int mm = 0; mm < NM; ++mm) {
+                    X[mm][k] = a[mm][r];
+                    Y[mm][k] = b[mm][r];
                 }
             }
         }
@@ -1654,15 +1662,13 @@ __device__ __attribute__((always_inline)) inline void blue_pass(float2 *X, float
     }
 }
 
-// The passes of one direction of a Bluestein fast-path ring's two
-// convolutions: sign -1 (forward, from the folded spectrum) or +1 (inverse,
-// ending in the pixel stores).
-template <int sign>
-__device__ __attribute__((always_inline)) inline void blue_dir(float2 *X, float2 *Y,
-                                                               const float2 *TW,
-                                                               const float2 *TB,
-                                                               const RingDesc &d,
-                                                               const BlueRing &br)
+// The passes of one direction of a Bluestein fast-path ring's convolutions:
+// sign -1 (forward, from the folded spectra) or +1 (inverse, ending in the
+// pixel stores).
+template <int sign, int NM>
+__device__ __attribute__((always_inline)) inline void blue_dir(
+    float2 *const (&X)[NM], float2 *const (&Y)[NM], const float2 *TW, const float2 *TB,
+    const RingDesc &d, const BlueRing &br, double *const (&out)[NM], int nout)
 {
     const int L = d.nb;
     int Ns = 1;
@@ -1671,12 +1677,12 @@ __device__ __attribute__((always_inline)) inline void blue_dir(float2 *X, float2
         const int in = (p > 0) ? kBlueInBuf : (sign < 0 ? kBlueInZ : kBlueInBq);
         const bool last = sign > 0 && p == d.np - 1;
         switch (R) {
-        case 8: blue_pass<8, sign>(X, Y, TW, TB, L, Ns, in, last, br); break;
-        case 4: blue_pass<4, sign>(X, Y, TW, TB, L, Ns, in, last, br); break;
-        case 2: blue_pass<2, sign>(X, Y, TW, TB, L, Ns, in, last, br); break;
-        case 7: blue_pass<7, sign>(X, Y, TW, TB, L, Ns, in, last, br); break;
-        case 5: blue_pass<5, sign>(X, Y, TW, TB, L, Ns, in, last, br); break;
-        default: blue_pass<3, sign>(X, Y, TW, TB, L, Ns, in, last, br); break;
+        case 8: blue_pass<8, sign, NM>(X, Y, TW, TB, L, Ns, in, last, br, out, nout); break;
+        case 4: blue_pass<4, sign, NM>(X, Y, TW, TB, L, Ns, in, last, br, out, nout); break;
+        case 2: blue_pass<2, sign, NM>(X, Y, TW, TB, L, Ns, in, last, br, out, nout); break;
+        case 7: blue_pass<7, sign, NM>(X, Y, TW, TB, L, Ns, in, last, br, out, nout); break;
+        case 5: blue_pass<5, sign, NM>(X, Y, TW, TB, L, Ns, in, last, br, out, nout); break;
+        default: blue_pass<3, sign, NM>(X, Y, TW, TB, L, Ns, in, last, br, out, nout); break;
         }
         Ns *= R;
     }
@@ -1715,7 +1721,7 @@ __global__ __launch_bounds__(kBlueThreads, 4) void k_ring_synth_blue(
         br.len = br.h / 2;
         br.inv_h = 1.0f / (float)br.h;
         br.bq = pool32 + d.bq;
-        br.out = map + b * npix + d.start;
+        double *const out[1] = {map + b * npix + d.start};
         if (!first) __syncthreads();   // the previous ring's last pass has read TW
         load_tw<kBlueThreads>(TW, pool32 + d.tw, d.n);
         load_tw<kBlueThreads>(TB, pool32 + d.twb, d.nb);
@@ -1728,8 +1734,9 @@ __global__ __launch_bounds__(kBlueThreads, 4) void k_ring_synth_blue(
             load_fast<kBlueThreads>(raw, delta + b * dl.map + r * dl.ring, dl.m, minv, mcontig,
                                     mmax);
         }
-        blue_dir<-1>(X, Y, TW, TB, d, br);
-        blue_dir<+1>(X, Y, TW, TB, d, br);
+        float2 *const Xs[1] = {X}, *const Ys[1] = {Y};
+        blue_dir<-1, 1>(Xs, Ys, TW, TB, d, br, out, 1);
+        blue_dir<+1, 1>(Xs, Ys, TW, TB, d, br, out, 1);
         if (nx >= hi) break;
         it = nx;
     }
@@ -1983,6 +1990,7 @@ hipError_t synth_blue_class(const sht_plan_s *p, const float2 *delta, double *ma
 {
     const RingClass &rc = p->scls[kBlueClass];
     if (rc.count == 0) return hipSuccess;
+    if (!p->d_pool32) return hipErrorInvalidConfiguration;
     const size_t lds = (size_t)rc.lds.total() * sizeof(float2);
     hipError_t e = set_lds((const void *)k_ring_synth_blue, lds);
     if (e != hipSuccess) return e;
