@@ -28,8 +28,9 @@
 // 16-byte load per mode) and runs the passes of both in complex64 (the fold
 // adds in FP64 either way).  The mixed forms also take even rings whose half
 // length is twice a non-7-smooth number on a Bluestein fast path: a
-// persistent 512-thread kernel that runs the even- and odd-indexed Bluestein
-// convolutions side by side in two complex64 buffers.  The other rings are
+// persistent 512-thread kernel that loads two maps of a ring per item and,
+// map by map, runs the even- and odd-indexed Bluestein convolutions side by
+// side in two complex64 buffers.  The other rings are
 // grouped by FFT length into three size classes (up to 2048, 4096 and 8192
 // points) run by 256-, 512- and 1024-thread workgroups, each with an LDS
 // layout computed on the host for the class.  There, DFTs of 7-smooth length run as
