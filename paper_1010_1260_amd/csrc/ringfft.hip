@@ -1975,7 +1975,7 @@ hipError_t synth_fast_class(const sht_plan_s *p, const DT *delta, double *map, h
     const size_t lds = (size_t)rc.lds.total() * sizeof(typename FastPrec<DT>::C);
     hipError_t e = set_lds((const void *)k_ring_synth_fast<DT>, lds);
     if (e != hipSuccess) return e;
-    // as many workgroups per CU as the LDS of a ring allows (2 or 4), a multiple of 8
+    // as many workgroups per CU as the LDS of a ring allows (two), a multiple of 8
     const long long items = (long long)rc.count * p->nmaps;
     long long grid = (long long)FastPrec<DT>::kBlocks * (p->num_cus > 0 ? p->num_cus : 256);
     if (grid > items) grid = items;
